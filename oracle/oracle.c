@@ -1,0 +1,637 @@
+/*
+ * oracle.c -- plain FP64 CPU oracle of the charge-transfer bond-order
+ * potential's energy, forces and charges.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  It shares no code, header,
+ * table or helper with the HIP library; the two meet only through the flat
+ * parameter vector and the seeded structure generators.
+ *
+ * What it computes, and where each part comes from:
+ *  - neighbours: every (j, image n) with |x_j + n.h - x_i| < cutoff, by brute
+ *    force over all atoms and images, or (for large inputs) by a separately
+ *    written cell list; self images (j == i, n != 0) are neighbours too;
+ *  - energy, forces and the charge solve: oracle_core.h (bond order from the
+ *    paper's Methods section, Eqs. 1-7; charges minimise the energy at fixed
+ *    total charge, Methods);
+ *  - velocity-Verlet NVE dynamics with fixed atoms (the paper fixes the
+ *    bottom of its SiC slab while the rest moves);
+ *  - parameter derivatives by complex-step differentiation of the same core.
+ *
+ * Units: Angstrom, eV, e, fs, amu.
+ */
+#define _GNU_SOURCE
+#include <complex.h>
+#include <math.h>
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------- */
+/* geometry (always real)                                                    */
+/* ------------------------------------------------------------------------- */
+
+typedef struct { int j; double d[3]; double r; } pr_t;   /* neighbour entry */
+typedef struct { int n; long *off; pr_t *p; } nlist_t;   /* CSR over atoms  */
+
+typedef struct {
+    double h[3][3];      /* rows: cell vectors */
+    double hi[3][3];     /* inverse: frac = x . hi */
+    double w[3];         /* perpendicular widths */
+    int pbc[3];
+} cell_t;
+
+static void cell_init(cell_t *c, const double *box, const int *pbc)
+{
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) c->h[a][b] = box[3 * a + b];
+    double (*h)[3] = c->h;
+    double det = h[0][0] * (h[1][1] * h[2][2] - h[1][2] * h[2][1])
+               - h[0][1] * (h[1][0] * h[2][2] - h[1][2] * h[2][0])
+               + h[0][2] * (h[1][0] * h[2][1] - h[1][1] * h[2][0]);
+    /* inverse of h (frac = x . hi, i.e. x = frac . h) */
+    c->hi[0][0] = (h[1][1] * h[2][2] - h[1][2] * h[2][1]) / det;
+    c->hi[0][1] = (h[0][2] * h[2][1] - h[0][1] * h[2][2]) / det;
+    c->hi[0][2] = (h[0][1] * h[1][2] - h[0][2] * h[1][1]) / det;
+    c->hi[1][0] = (h[1][2] * h[2][0] - h[1][0] * h[2][2]) / det;
+    c->hi[1][1] = (h[0][0] * h[2][2] - h[0][2] * h[2][0]) / det;
+    c->hi[1][2] = (h[0][2] * h[1][0] - h[0][0] * h[1][2]) / det;
+    c->hi[2][0] = (h[1][0] * h[2][1] - h[1][1] * h[2][0]) / det;
+    c->hi[2][1] = (h[0][1] * h[2][0] - h[0][0] * h[2][1]) / det;
+    c->hi[2][2] = (h[0][0] * h[1][1] - h[0][1] * h[1][0]) / det;
+    for (int a = 0; a < 3; a++) {
+        const double *u = h[(a + 1) % 3], *v = h[(a + 2) % 3];
+        double cx = u[1] * v[2] - u[2] * v[1], cy = u[2] * v[0] - u[0] * v[2], cz = u[0] * v[1] - u[1] * v[0];
+        c->w[a] = fabs(det) / sqrt(cx * cx + cy * cy + cz * cz);
+        c->pbc[a] = pbc[a] ? 1 : 0;
+    }
+}
+
+static void to_frac(const cell_t *c, const double *x, double *s)
+{
+    for (int b = 0; b < 3; b++) s[b] = x[0] * c->hi[0][b] + x[1] * c->hi[1][b] + x[2] * c->hi[2][b];
+}
+
+static void to_cart(const cell_t *c, const double *s, double *x)
+{
+    for (int b = 0; b < 3; b++) x[b] = s[0] * c->h[0][b] + s[1] * c->h[1][b] + s[2] * c->h[2][b];
+}
+
+/* positions folded into the cell along periodic vectors */
+static double *wrapped(const cell_t *c, int n, const double *pos)
+{
+    double *xw = malloc(sizeof(double) * 3 * n);
+    for (int i = 0; i < n; i++) {
+        double s[3];
+        to_frac(c, pos + 3 * i, s);
+        for (int a = 0; a < 3; a++) if (c->pbc[a]) s[a] -= floor(s[a]);
+        to_cart(c, s, xw + 3 * i);
+    }
+    return xw;
+}
+
+static void nl_free(nlist_t *L)
+{
+    free(L->off);
+    free(L->p);
+    L->off = NULL;
+    L->p = NULL;
+}
+
+/* Brute force: all atoms j and all images n with |n_a| <= ceil(rc/w_a) + 1
+ * along periodic vectors.  Two passes (count, fill) so rows are independent. */
+static void nl_brute(const cell_t *c, int n, const double *pos, double rc, nlist_t *L)
+{
+    double *xw = wrapped(c, n, pos);
+    int M[3];
+    for (int a = 0; a < 3; a++) M[a] = c->pbc[a] ? (int)ceil(rc / c->w[a]) + 1 : 0;
+    L->n = n;
+    L->off = calloc(n + 1, sizeof(long));
+    long *cnt = calloc(n, sizeof(long));
+    const double rc2 = rc * rc;
+    for (int pass = 0; pass < 2; pass++) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int i = 0; i < n; i++) {
+            long k = pass ? L->off[i] : 0;
+            for (int j = 0; j < n; j++)
+                for (int n0 = -M[0]; n0 <= M[0]; n0++)
+                    for (int n1 = -M[1]; n1 <= M[1]; n1++)
+                        for (int n2 = -M[2]; n2 <= M[2]; n2++) {
+                            if (j == i && n0 == 0 && n1 == 0 && n2 == 0) continue;
+                            double d[3];
+                            for (int a = 0; a < 3; a++)
+                                d[a] = xw[3 * j + a] + n0 * c->h[0][a] + n1 * c->h[1][a] + n2 * c->h[2][a] - xw[3 * i + a];
+                            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                            if (r2 >= rc2) continue;
+                            if (pass) {
+                                pr_t *e = &L->p[k];
+                                e->j = j;
+                                memcpy(e->d, d, sizeof d);
+                                e->r = sqrt(r2);
+                            }
+                            k++;
+                        }
+            if (!pass) cnt[i] = k;
+        }
+        if (!pass) {
+            for (int i = 0; i < n; i++) L->off[i + 1] = L->off[i] + cnt[i];
+            L->p = malloc(sizeof(pr_t) * (L->off[n] > 0 ? L->off[n] : 1));
+        }
+    }
+    free(cnt);
+    free(xw);
+}
+
+/* Cell list with cells at least rc wide and a +-1 stencil.  Needs >= 3 cells
+ * along every periodic vector (returns -1 otherwise).  Along non-periodic
+ * vectors the cells span the atoms' range. */
+static int nl_cells(const cell_t *c, int n, const double *pos, double rc, nlist_t *L)
+{
+    double *xw = wrapped(c, n, pos);
+    double *s = malloc(sizeof(double) * 3 * n);
+    for (int i = 0; i < n; i++) to_frac(c, xw + 3 * i, s + 3 * i);
+    double lo[3], hi[3];
+    int nb[3];
+    for (int a = 0; a < 3; a++) {
+        if (c->pbc[a]) {
+            lo[a] = 0.0; hi[a] = 1.0;
+            nb[a] = (int)floor(c->w[a] / rc);
+            if (nb[a] < 3) { free(s); free(xw); return -1; }
+        } else {
+            lo[a] = 1e300; hi[a] = -1e300;
+            for (int i = 0; i < n; i++) { lo[a] = fmin(lo[a], s[3 * i + a]); hi[a] = fmax(hi[a], s[3 * i + a]); }
+            double ext = (hi[a] - lo[a]) * c->w[a];
+            nb[a] = (int)floor(ext / rc);
+            if (nb[a] < 1) nb[a] = 1;
+            hi[a] = lo[a] + fmax(hi[a] - lo[a], 1e-12);
+        }
+    }
+    long ncell = (long)nb[0] * nb[1] * nb[2];
+    int *cid = malloc(sizeof(int) * n);
+    long *head = calloc(ncell + 1, sizeof(long));
+    for (int i = 0; i < n; i++) {
+        int ci[3];
+        for (int a = 0; a < 3; a++) {
+            int v = (int)floor((s[3 * i + a] - lo[a]) / (hi[a] - lo[a]) * nb[a]);
+            ci[a] = v < 0 ? 0 : (v >= nb[a] ? nb[a] - 1 : v);
+        }
+        cid[i] = (ci[0] * nb[1] + ci[1]) * nb[2] + ci[2];
+        head[cid[i] + 1]++;
+    }
+    for (long k = 0; k < ncell; k++) head[k + 1] += head[k];
+    int *members = malloc(sizeof(int) * n);
+    long *fill = calloc(ncell, sizeof(long));
+    for (int i = 0; i < n; i++) members[head[cid[i]] + fill[cid[i]]++] = i;
+    free(fill);
+
+    L->n = n;
+    L->off = calloc(n + 1, sizeof(long));
+    long *cnt = calloc(n, sizeof(long));
+    const double rc2 = rc * rc;
+    for (int pass = 0; pass < 2; pass++) {
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int i = 0; i < n; i++) {
+            long k = pass ? L->off[i] : 0;
+            int c0 = cid[i] / (nb[1] * nb[2]), c1 = (cid[i] / nb[2]) % nb[1], c2 = cid[i] % nb[2];
+            for (int d0 = -1; d0 <= 1; d0++)
+                for (int d1 = -1; d1 <= 1; d1++)
+                    for (int d2 = -1; d2 <= 1; d2++) {
+                        int cc[3] = {c0 + d0, c1 + d1, c2 + d2}, im[3] = {0, 0, 0}, skip = 0;
+                        for (int a = 0; a < 3; a++) {
+                            if (cc[a] < 0 || cc[a] >= nb[a]) {
+                                if (!c->pbc[a]) { skip = 1; break; }
+                                im[a] = cc[a] < 0 ? -1 : 1;
+                                cc[a] -= im[a] * nb[a];
+                            }
+                        }
+                        if (skip) continue;
+                        long cell = ((long)cc[0] * nb[1] + cc[1]) * nb[2] + cc[2];
+                        for (long m = head[cell]; m < head[cell + 1]; m++) {
+                            int j = members[m];
+                            if (j == i && im[0] == 0 && im[1] == 0 && im[2] == 0) continue;
+                            double d[3];
+                            for (int a = 0; a < 3; a++)
+                                d[a] = xw[3 * j + a] + im[0] * c->h[0][a] + im[1] * c->h[1][a] + im[2] * c->h[2][a] - xw[3 * i + a];
+                            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                            if (r2 >= rc2) continue;
+                            if (pass) {
+                                pr_t *e = &L->p[k];
+                                e->j = j;
+                                memcpy(e->d, d, sizeof d);
+                                e->r = sqrt(r2);
+                            }
+                            k++;
+                        }
+                    }
+            if (!pass) cnt[i] = k;
+        }
+        if (!pass) {
+            for (int i = 0; i < n; i++) L->off[i + 1] = L->off[i] + cnt[i];
+            L->p = malloc(sizeof(pr_t) * (L->off[n] > 0 ? L->off[n] : 1));
+        }
+    }
+    free(cnt); free(members); free(head); free(cid); free(s); free(xw);
+    return 0;
+}
+
+/* method: 0 = brute force, 1 = cell list, -1 = cell list when it applies and
+ * n > 2000, brute force otherwise */
+static void nl_build(const cell_t *c, int n, const double *pos, double rc, int method, nlist_t *L)
+{
+    if (method == 1 || (method < 0 && n > 2000)) {
+        if (nl_cells(c, n, pos, rc, L) == 0) return;
+    }
+    nl_brute(c, n, pos, rc, L);
+}
+
+/* sub-list of entries with r < rc2 (the short list from the long one) */
+static void nl_filter(const nlist_t *A, double rc, nlist_t *B)
+{
+    int n = A->n;
+    B->n = n;
+    B->off = calloc(n + 1, sizeof(long));
+    for (int i = 0; i < n; i++) {
+        long k = 0;
+        for (long e = A->off[i]; e < A->off[i + 1]; e++) if (A->p[e].r < rc) k++;
+        B->off[i + 1] = B->off[i] + k;
+    }
+    B->p = malloc(sizeof(pr_t) * (B->off[n] > 0 ? B->off[n] : 1));
+    for (int i = 0; i < n; i++) {
+        long k = B->off[i];
+        for (long e = A->off[i]; e < A->off[i + 1]; e++) if (A->p[e].r < rc) B->p[k++] = A->p[e];
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* the scalar-generic core, real and complex                                 */
+/* ------------------------------------------------------------------------- */
+
+#define SC double
+#define FN(x) x##_r
+#define RE(x) (x)
+#define IM(x) (0.0)
+#define SEXP exp
+#define SCOS cos
+#define SSIN sin
+#define SPOW pow
+#define SSQRT sqrt
+#include "oracle_core.h"
+#undef SC
+#undef FN
+#undef RE
+#undef IM
+#undef SEXP
+#undef SCOS
+#undef SSIN
+#undef SPOW
+#undef SSQRT
+
+#define OR_COMPLEX 1
+#define SC double complex
+#define FN(x) x##_c
+#define RE(x) creal(x)
+#define IM(x) cimag(x)
+#define SEXP cexp
+#define SCOS ccos
+#define SSIN csin
+#define SPOW cpow
+#define SSQRT csqrt
+#include "oracle_core.h"
+
+/* ------------------------------------------------------------------------- */
+/* exported entry points                                                     */
+/* ------------------------------------------------------------------------- */
+
+static double short_cut(const prm_t_r *P)
+{
+    double s = 0.0;
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++) s = fmax(s, sqrt(P->sp[a].S * P->sp[b].S));
+    return s;
+}
+
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Full evaluation.  pos: n x 3 (row-major), box: 3 x 3 rows, pbc[3].
+ * q_io: in = initial charges (warm start), out = equilibrated charges.
+ * Outputs E (scalar), F (n x 3), eat (per-atom energy, may be NULL).
+ * info[0] = CG iterations (-1: not converged), info[1] = final RMS projected
+ * residual, info[2] = mu, info[3] = long-list entries, info[4] = short entries. */
+int oracle_eval(int n, const double *pos, const int *types, const double *box, const int *pbc,
+                const double *params, double Q, double tol, int maxit, int method,
+                double *q_io, double *E, double *F, double *eat, double *info)
+{
+    prm_t_r P;
+    read_params_r(params, -1, 0.0, &P);
+    cell_t c;
+    cell_init(&c, box, pbc);
+    nlist_t Ll, Ls;
+    nl_build(&c, n, pos, P.rc, method, &Ll);
+    nl_filter(&Ll, short_cut(&P), &Ls);
+    double *Hv = malloc(sizeof(double) * (Ll.off[n] > 0 ? Ll.off[n] : 1));
+    assemble_r(&P, n, types, &Ll, Hv);
+    double res = 0.0, mu = 0.0;
+    int it = qeq_solve_r(&P, n, types, &Ll, Hv, Q, tol, maxit, 0.0, q_io, &res, &mu);
+    if (F) memset(F, 0, sizeof(double) * 3 * n);
+    double *ea = calloc(n, sizeof(double));
+    double Ec = covalent_r(&P, n, types, &Ls, ea, F);
+    double Eq = charge_terms_r(&P, n, types, &Ll, q_io, ea, F);
+    *E = Ec + Eq;
+    if (eat) memcpy(eat, ea, sizeof(double) * n);
+    if (info) {
+        info[0] = it; info[1] = res; info[2] = mu;
+        info[3] = (double)Ll.off[n]; info[4] = (double)Ls.off[n];
+    }
+    free(ea); free(Hv);
+    nl_free(&Ll); nl_free(&Ls);
+    return it >= 0 ? 0 : 1;
+}
+
+/* Energy and forces at given charges (no charge solve). */
+int oracle_eval_fixed_q(int n, const double *pos, const int *types, const double *box, const int *pbc,
+                        const double *params, const double *q, int method, double *E, double *F,
+                        double *eat)
+{
+    prm_t_r P;
+    read_params_r(params, -1, 0.0, &P);
+    cell_t c;
+    cell_init(&c, box, pbc);
+    nlist_t Ll, Ls;
+    nl_build(&c, n, pos, P.rc, method, &Ll);
+    nl_filter(&Ll, short_cut(&P), &Ls);
+    if (F) memset(F, 0, sizeof(double) * 3 * n);
+    double *ea = calloc(n, sizeof(double));
+    double Ec = covalent_r(&P, n, types, &Ls, ea, F);
+    double Eq = charge_terms_r(&P, n, types, &Ll, q, ea, F);
+    *E = Ec + Eq;
+    if (eat) memcpy(eat, ea, sizeof(double) * n);
+    free(ea);
+    nl_free(&Ll); nl_free(&Ls);
+    return 0;
+}
+
+/* Dense charge-equilibration matrix H (n x n, row-major) and chi (n): for the
+ * direct KKT solve and eigenvalue checks on small inputs. */
+int oracle_dense_h(int n, const double *pos, const int *types, const double *box, const int *pbc,
+                   const double *params, double *H, double *chi)
+{
+    prm_t_r P;
+    read_params_r(params, -1, 0.0, &P);
+    cell_t c;
+    cell_init(&c, box, pbc);
+    nlist_t L;
+    nl_brute(&c, n, pos, P.rc, &L);
+    memset(H, 0, sizeof(double) * n * n);
+    for (int i = 0; i < n; i++) {
+        H[(long)i * n + i] += P.sp[types[i]].J;
+        chi[i] = P.sp[types[i]].chi;
+        for (long e = L.off[i]; e < L.off[i + 1]; e++)
+            H[(long)i * n + L.p[e].j] += coul_r(&P, types[i], types[L.p[e].j], L.p[e].r, NULL);
+    }
+    nl_free(&L);
+    return 0;
+}
+
+/* Bond order of species t for given zeta_1, zeta_2 (and its derivatives). */
+double oracle_bond_order(const double *params, int t, double z1, double z2, double *db)
+{
+    prm_t_r P;
+    read_params_r(params, -1, 0.0, &P);
+    double z[2] = {z1, z2}, d[2];
+    double b = bond_order_r(&P.sp[t], P.p, z, d);
+    if (db) { db[0] = d[0]; db[1] = d[1]; }
+    return b;
+}
+
+/* Angular function w_l of species t at cos(theta). */
+double oracle_angular(const double *params, int t, int l, double cs)
+{
+    prm_t_r P;
+    read_params_r(params, -1, 0.0, &P);
+    return wang_r(&P.sp[t], l, cs);
+}
+
+/* Coulomb kernel C_ij(r) and its derivative. */
+double oracle_coulomb(const double *params, int ti, int tj, double r, double *dC)
+{
+    prm_t_r P;
+    read_params_r(params, -1, 0.0, &P);
+    return coul_r(&P, ti, tj, r, dC);
+}
+
+/* Neighbour list export: counts[n] and, if js != NULL, for every entry the
+ * neighbour index and its displacement vector (rows in CSR order). */
+long oracle_neighbors(int n, const double *pos, const double *box, const int *pbc, double rc,
+                      int method, long *counts, int *js, double *dvec)
+{
+    cell_t c;
+    cell_init(&c, box, pbc);
+    nlist_t L;
+    nl_build(&c, n, pos, rc, method, &L);
+    long tot = L.off[n];
+    for (int i = 0; i < n; i++) counts[i] = L.off[i + 1] - L.off[i];
+    if (js)
+        for (long e = 0; e < tot; e++) {
+            js[e] = L.p[e].j;
+            memcpy(dvec + 3 * e, L.p[e].d, 3 * sizeof(double));
+        }
+    nl_free(&L);
+    return tot;
+}
+
+/* Per-atom quantities for a sample of atoms, given charges q for every atom
+ * (e.g. a GPU solution), without solving for the charges:
+ *   g[s]    = chi_i + (H q)_i   (the charge-equilibration gradient; at the
+ *             solution every entry equals mu)
+ *   Fs[3s]  = force on atom i (covalent + Coulomb at the given charges)
+ *   es[s]   = per-atom energy share of atom i
+ * The covalent force on i is taken from a cluster of all atoms within twice
+ * the covalent cutoff of i (every term that moves with x_i lies inside it). */
+int oracle_sample(int n, const double *pos, const int *types, const double *box, const int *pbc,
+                  const double *params, const double *q, int ns, const int *idx,
+                  double *g, double *Fs, double *es)
+{
+    prm_t_r P;
+    read_params_r(params, -1, 0.0, &P);
+    cell_t c;
+    cell_init(&c, box, pbc);
+    const double rs = short_cut(&P);
+    const double rclu = fmax(P.rc, 2.0 * rs + 1e-6);
+    nlist_t L;
+    nl_build(&c, n, pos, rclu, -1, &L);
+    for (int s = 0; s < ns; s++) {
+        int i = idx[s];
+        const sp_t_r *si = &P.sp[types[i]];
+        double gi = si->chi + si->J * q[i], f[3] = {0, 0, 0};
+        double ei = si->E0 + si->chi * q[i] + 0.5 * si->J * q[i] * q[i];
+        int m = 1;
+        for (long e = L.off[i]; e < L.off[i + 1]; e++) {
+            const pr_t *p = &L.p[e];
+            if (p->r < P.rc) {
+                double dC, Cv = coul_r(&P, types[i], types[p->j], p->r, &dC);
+                gi += Cv * q[p->j];
+                ei += 0.5 * q[i] * q[p->j] * Cv;
+                if (p->j != i)
+                    for (int a = 0; a < 3; a++) f[a] += q[i] * q[p->j] * dC * p->d[a] / p->r;
+            }
+            if (p->r < 2.0 * rs + 1e-6) m++;
+        }
+        /* local cluster: atom i at the origin plus every image within 2 rs */
+        double *cp = malloc(sizeof(double) * 3 * m);
+        int *ct = malloc(sizeof(int) * m);
+        cp[0] = cp[1] = cp[2] = 0.0;
+        ct[0] = types[i];
+        int k = 1;
+        for (long e = L.off[i]; e < L.off[i + 1]; e++)
+            if (L.p[e].r < 2.0 * rs + 1e-6) {
+                memcpy(cp + 3 * k, L.p[e].d, 3 * sizeof(double));
+                ct[k++] = types[L.p[e].j];
+            }
+        double bx[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+        int nop[3] = {0, 0, 0};
+        cell_t cc;
+        cell_init(&cc, bx, nop);
+        nlist_t Lc;
+        nl_brute(&cc, m, cp, rs, &Lc);
+        double *Fc = calloc(3 * m, sizeof(double));
+        double *ea = calloc(m, sizeof(double));
+        covalent_r(&P, m, ct, &Lc, ea, Fc);
+        if (g) g[s] = gi;
+        if (Fs) for (int a = 0; a < 3; a++) Fs[3 * s + a] = f[a] + Fc[a];
+        if (es) es[s] = ei + ea[0];
+        free(ea); free(Fc); free(cp); free(ct);
+        nl_free(&Lc);
+    }
+    nl_free(&L);
+    return 0;
+}
+
+/* Total energy at given charges, streamed per atom without storing the long
+ * list (for inputs too large for oracle_eval's memory). */
+double oracle_energy_at_q(int n, const double *pos, const int *types, const double *box,
+                          const int *pbc, const double *params, const double *q, double *eat)
+{
+    prm_t_r P;
+    read_params_r(params, -1, 0.0, &P);
+    cell_t c;
+    cell_init(&c, box, pbc);
+    nlist_t Ls;
+    nl_build(&c, n, pos, short_cut(&P), -1, &Ls);
+    double *ea = calloc(n, sizeof(double));
+    covalent_r(&P, n, types, &Ls, ea, NULL);
+    nl_free(&Ls);
+    nlist_t Ll;
+    nl_build(&c, n, pos, P.rc, -1, &Ll);
+    charge_terms_r(&P, n, types, &Ll, q, ea, NULL);
+    nl_free(&Ll);
+    double E = 0.0;
+    for (int i = 0; i < n; i++) E += ea[i];
+    if (eat) memcpy(eat, ea, sizeof(double) * n);
+    free(ea);
+    return E;
+}
+
+/* Velocity-Verlet NVE: half kick, drift, new forces (charges re-equilibrated,
+ * warm-started), half kick.  Fixed atoms (fixed[i] != 0) neither move nor
+ * change velocity but still interact.  Velocities in Angstrom/fs.
+ * Etraj[s] (s = 0..nsteps) = potential + kinetic energy after step s. */
+int oracle_md_nve(int n, double *pos, double *vel, const int *types, const int *fixed,
+                  const double *box, const int *pbc, const double *params, double Q, double dt,
+                  int nsteps, double tol, double *q_io, double *Etraj, double *Epot)
+{
+    const double acc = 9.648533212e-3;        /* (eV/Angstrom)/amu in Angstrom/fs^2 */
+    prm_t_r P;
+    read_params_r(params, -1, 0.0, &P);
+    double *F = malloc(sizeof(double) * 3 * n), E;
+    double info[5];
+    if (oracle_eval(n, pos, types, box, pbc, params, Q, tol, 2000, -1, q_io, &E, F, NULL, info)) {
+        free(F);
+        return 1;
+    }
+    for (int s = 0; s <= nsteps; s++) {
+        if (s > 0) {
+            for (int i = 0; i < n; i++) {
+                if (fixed && fixed[i]) continue;
+                double m = P.sp[types[i]].mass;
+                for (int a = 0; a < 3; a++) {
+                    vel[3 * i + a] += 0.5 * dt * acc * F[3 * i + a] / m;
+                    pos[3 * i + a] += dt * vel[3 * i + a];
+                }
+            }
+            if (oracle_eval(n, pos, types, box, pbc, params, Q, tol, 2000, -1, q_io, &E, F, NULL, info)) {
+                free(F);
+                return 1;
+            }
+            for (int i = 0; i < n; i++) {
+                if (fixed && fixed[i]) continue;
+                double m = P.sp[types[i]].mass;
+                for (int a = 0; a < 3; a++) vel[3 * i + a] += 0.5 * dt * acc * F[3 * i + a] / m;
+            }
+        }
+        double ke = 0.0;
+        for (int i = 0; i < n; i++) {
+            double m = P.sp[types[i]].mass;
+            for (int a = 0; a < 3; a++) ke += 0.5 * m * vel[3 * i + a] * vel[3 * i + a] / acc;
+        }
+        if (Etraj) Etraj[s] = E + ke;
+        if (Epot) Epot[s] = E;
+    }
+    free(F);
+    return 0;
+}
+
+/* Parameter derivatives by complex step: for parameter k, dE/dtheta_k,
+ * dF/dtheta_k (n x 3) and dq/dtheta_k (n), all at the equilibrated charges
+ * (the charge solve is redone in complex arithmetic, so the charges' response
+ * to theta_k is included).  h is the imaginary step (e.g. 1e-30). */
+int oracle_param_derivative(int n, const double *pos, const int *types, const double *box,
+                            const int *pbc, const double *params, double Q, double tol, int k,
+                            double h, double *dE, double *dF, double *dq, double *E, double *F,
+                            double *q)
+{
+    prm_t_c P;
+    read_params_c(params, k, h, &P);
+    prm_t_r Pr;
+    read_params_r(params, -1, 0.0, &Pr);
+    cell_t c;
+    cell_init(&c, box, pbc);
+    nlist_t Ll, Ls;
+    nl_build(&c, n, pos, creal(P.rc), -1, &Ll);
+    nl_filter(&Ll, short_cut(&Pr), &Ls);
+    double complex *Hv = malloc(sizeof(double complex) * (Ll.off[n] > 0 ? Ll.off[n] : 1));
+    assemble_c(&P, n, types, &Ll, Hv);
+    double complex *qc = calloc(n, sizeof(double complex));
+    double res;
+    double complex mu;
+    int it = qeq_solve_c(&P, n, types, &Ll, Hv, Q, tol, 5000, h, qc, &res, &mu);
+    double complex *Fc = calloc(3 * n, sizeof(double complex));
+    double complex Ec = covalent_c(&P, n, types, &Ls, NULL, Fc);
+    double complex Eq = charge_terms_c(&P, n, types, &Ll, qc, NULL, Fc);
+    double complex Et = Ec + Eq;
+    if (dE) *dE = cimag(Et) / h;
+    if (E) *E = creal(Et);
+    for (int i = 0; i < n; i++) {
+        if (dq) dq[i] = cimag(qc[i]) / h;
+        if (q) q[i] = creal(qc[i]);
+        for (int a = 0; a < 3; a++) {
+            if (dF) dF[3 * i + a] = cimag(Fc[3 * i + a]) / h;
+            if (F) F[3 * i + a] = creal(Fc[3 * i + a]);
+        }
+    }
+    free(Fc); free(qc); free(Hv);
+    nl_free(&Ll); nl_free(&Ls);
+    return it >= 0 ? 0 : 1;
+}
