@@ -1,0 +1,187 @@
+/*
+ * ctbop.h -- C ABI of the MI355X (gfx950) library for the charge-transfer
+ * bond-order potential of Si-C (Takamoto et al., arXiv:1802.07871).
+ *
+ * One call evaluates, for a configuration of atoms, the total energy E, the
+ * forces F = -dE/dx and the equilibrated charges q:
+ *
+ *   E(x) = min over q with sum q = Q of
+ *          sum_i [E0_i + chi_i q_i + J_i q_i^2 / 2]
+ *        + 1/2 sum_i sum_(j,n)!=(i,0) q_i q_j C_ij(|x_j + n.h - x_i|)
+ *        + 1/2 sum_i sum_(j,n) fc(r) [fR(r) - b_ij fA(r)]
+ *
+ * with the paper's vectorised bond order b_ij (Methods, Eqs. 3-5, expanded as
+ * Eq. 7 with two channels and p = 2, normalised so b = 1 without neighbours),
+ * environment sums zeta_l,ij over third atoms k (Eq. 2), and the charges
+ * minimising the energy at every call (Methods: charges are minimised by
+ * conjugate gradients at every step, a constant term E0 sits in the self
+ * energy).  The pair terms, angular functions and the shielded, tapered
+ * Coulomb kernel C_ij are the stand-in forms documented with the parameter
+ * layout below.
+ *
+ * Conventions
+ *   units      Angstrom, eV, e, fs, amu; Coulomb constant is parameter "ke".
+ *   types      int32, 0 = Si, 1 = C.
+ *   box        host double[9], three cell vectors as rows (x = frac . box),
+ *              right-handed; pbc host int[3], nonzero = periodic along that
+ *              vector.  Along a non-periodic vector the box should enclose the
+ *              atoms (atoms outside are still handled, only more slowly).
+ *              Every periodic vector's perpendicular width must be at least
+ *              (rc_coul + skin) / 3.
+ *   arrays     "_dev" pointers are device memory (HIP), "_host" host memory.
+ *              Positions, forces and velocities are SoA: x[0..n), y[0..n),
+ *              z[0..n) contiguous (3n doubles).
+ *   ownership  every device byte is the caller's: inputs, outputs and the
+ *              per-system buffer `sys` (lists, charges for the warm start,
+ *              scratch).  The library never allocates device memory.  A
+ *              context holds only host-side parameters and options.
+ *   streams    every call enqueues work on the caller's stream (hipStream_t
+ *              passed as void*, NULL = default stream).  The charge solve
+ *              stops on a device-side test, so the host waits on that stream
+ *              between batches of solver iterations (cg_check) to read the
+ *              flag; with info != NULL it also waits at the end to report.
+ *   errors     every function returns a status; 0 = CTBOP_OK.  Errors found on
+ *              the device (close contacts, list overflow, charge solve not
+ *              converged or not positive definite) land in a status word in
+ *              `sys`; they are returned when info != NULL, else read later
+ *              with ctbop_status().  On error, outputs are unspecified.
+ *              ctbop_last_error() gives a message for the calling thread.
+ *
+ * Parameter vector (CTBOP_N_PARAMS = 56 doubles), species base = 26 * t:
+ *   base+0 A  +1 B  +2 lam1  +3 lam2  +4 R  +5 S  +6 sigma
+ *   base+7..13  channel 1: gamma c d h n g alpha
+ *   base+14..20 channel 2: gamma c d h n g alpha
+ *   base+21 chi  +22 J  +23 gamma_coul  +24 E0  +25 mass
+ *   52 B_mix_SiC  53 ke  54 rc_coul  55 p
+ * Pair terms fR = A_ij exp(-lam1_ij r), fA = B_ij exp(-lam2_ij r) with A, B, R,
+ * S geometric and lam arithmetic means (B_ij times B_mix_SiC for Si-C);
+ * fc = 1 below R_ij, 0 above S_ij, half-cosine in between.  Channel l of the
+ * centre atom's species: zeta_l,ij = sum_k fc(r_ik) w_l(cos theta_ijk)
+ * exp[(alpha_l (r_ij - r_ik))^3], w_l = gamma_l [1 + c_l^2 x^2 / (d_l^2 (d_l^2
+ * + x^2))], x = h_l - cos theta.  b_ij = G (sum_l (g_l + zeta_l^n_l)^-p)^(1/(2
+ * sigma p)).  Coulomb C_ij(r) = ke T(r/rc) (r^3 + (gamma_i gamma_j)^-3/2)^-1/3
+ * with T(x) = (1-x)^4 (1 + 4x + 10x^2 + 20x^3) below the cutoff.
+ */
+#ifndef CTBOP_H
+#define CTBOP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CTBOP_N_PARAMS 56
+
+/* status codes */
+#define CTBOP_OK               0
+#define CTBOP_E_INVAL          1   /* bad argument or geometry                 */
+#define CTBOP_E_NOMEM          2   /* sys buffer too small for this system     */
+#define CTBOP_E_TOO_CLOSE      3   /* two atoms closer than 0.5 Angstrom        */
+#define CTBOP_E_QEQ_NOCONV     4   /* charge solve hit cg_maxit                 */
+#define CTBOP_E_QEQ_NOT_PD     5   /* p^T H p <= 0 met in the charge solve      */
+#define CTBOP_E_NEIGH_OVERFLOW 6   /* more neighbours than the list capacity    */
+#define CTBOP_E_HIP            7   /* a HIP runtime call failed                 */
+#define CTBOP_E_BUSY           8   /* serving: request not admitted right now   */
+
+/* flags of ctbop_compute_energy_forces_charges */
+#define CTBOP_FLAG_WARM_START    1  /* start the charge solve from the last call's charges */
+#define CTBOP_FLAG_FORCE_REBUILD 2  /* rebuild cell bins and lists regardless of motion   */
+
+typedef struct ctbop_ctx ctbop_ctx;
+
+typedef struct {
+    double cg_tol;     /* stop when RMS of the projected charge residual < cg_tol (eV/e); default 1e-9 */
+    int    cg_maxit;   /* default 500                                                            */
+    double skin;       /* Verlet skin (Angstrom): lists are rebuilt once an atom moved skin/2; 0.5 */
+    int    long_cap;   /* Coulomb-list entries per atom (0: 512)                                  */
+    int    short_cap;  /* covalent-list entries per atom (0: 64)                                  */
+    int    fp64;       /* 1: every pair/triplet term in FP64 (default 0: FP32 terms, FP64 sums)   */
+    int    cg_check;   /* charge-solve iterations launched between convergence checks (0: 4)    */
+} ctbop_opts;
+
+typedef struct {
+    double energy;      /* total energy (eV)                                   */
+    double cg_residual; /* final RMS projected residual of the charge solve    */
+    double mu;          /* chemical potential (eV/e) at the solution           */
+    int    cg_iters;
+    int    rebuilt;     /* 1 if this call rebuilt bins and lists               */
+    int    status;      /* device status word (CTBOP_* code)                   */
+    int    max_long;    /* largest Coulomb-list row at the last rebuild        */
+    int    max_short;   /* largest covalent-list row at the last rebuild       */
+    unsigned long long nnz_long;   /* Coulomb-list entries at the last rebuild  */
+    unsigned long long nnz_short;  /* covalent-list entries at the last rebuild */
+} ctbop_info;
+
+/* Fill *o with the defaults above. */
+void ctbop_default_opts(ctbop_opts *o);
+
+/* Create a context from the flat parameter vector (host, n_params doubles,
+ * copied) and options (may be NULL for defaults).  E_INVAL on a malformed
+ * vector (n_params != CTBOP_N_PARAMS, non-positive sigma/n/g/p/J). */
+int ctbop_create(const double *params_host, int n_params, const ctbop_opts *opts, ctbop_ctx **ctx);
+int ctbop_destroy(ctbop_ctx *ctx);
+
+/* Bytes of the per-system device buffer for n atoms in this cell.  The buffer
+ * is reused across calls for the same system (it keeps the lists, the sort
+ * order and the charges for the warm start); its content is opaque. */
+int ctbop_system_bytes(ctbop_ctx *ctx, int n, const double *box_host, const int *pbc_host, size_t *bytes);
+
+/* Energy, forces and charges (the hot path).
+ *   pos_dev   double[3n] SoA positions (any periodic image)
+ *   types_dev int32[n]
+ *   E_dev     double[1] out; F_dev double[3n] SoA out; q_dev double[n] out
+ *   sys_dev   caller buffer of at least ctbop_system_bytes() bytes; pass the
+ *             same buffer for successive calls on one system
+ *   info      host pointer or NULL (NULL: no final wait or report)       */
+int ctbop_compute_energy_forces_charges(ctbop_ctx *ctx, int n, const double *pos_dev,
+                                        const int32_t *types_dev, const double *box_host,
+                                        const int *pbc_host, double total_charge, int flags,
+                                        void *sys_dev, size_t sys_bytes, double *E_dev,
+                                        double *F_dev, double *q_dev, ctbop_info *info,
+                                        void *stream);
+
+/* Velocity-Verlet NVE for nsteps of dt_fs, re-evaluating energy, forces and
+ * charges (warm-started) every step, lists rebuilt when an atom moved skin/2.
+ * x_dev, v_dev (SoA, Angstrom and Angstrom/fs) are updated in place; F_dev
+ * (SoA) and q_dev hold the final step's forces and charges; fixed_dev
+ * (uint8[n] or NULL): nonzero atoms neither move nor change velocity but
+ * still interact (the paper fixes its slab's bottom).  thermo_host (or NULL)
+ * receives, for s = 0, every, 2*every, ..., nsteps, the pair (E_pot, E_kin)
+ * in eV: 2 * (nsteps / every + 1) doubles.  Waits for the stream at the end. */
+int ctbop_md_run(ctbop_ctx *ctx, int n, double *x_dev, double *v_dev, const int32_t *types_dev,
+                 const uint8_t *fixed_dev, const double *box_host, const int *pbc_host,
+                 double total_charge, double dt_fs, int nsteps, int thermo_every,
+                 void *sys_dev, size_t sys_bytes, double *F_dev, double *q_dev,
+                 double *thermo_host, ctbop_info *info, void *stream);
+
+/* Device status word of `sys` (waits for the stream). */
+int ctbop_status(ctbop_ctx *ctx, void *sys_dev, size_t sys_bytes, void *stream, int *code);
+
+/* Per-kernel timing with HIP events recorded on the caller's stream around
+ * each launch (for measurement; off by default).  Waits for `stream`, folds
+ * finished timings in, copies accumulated milliseconds and launch counts of
+ * the first nk kernel classes to ms_out / count_out (host, may be NULL),
+ * clears them if reset != 0, then turns timing on (enable != 0) or off.
+ * Classes: 0 charge-solve matrix-vector product, 1 Coulomb force/energy
+ * gather, 2 Coulomb matrix assembly, 3 covalent bond pass, 4 covalent force
+ * gather, 5 charge-solve update, 6 charge-solve direction, 7 list build. */
+int ctbop_profile(ctbop_ctx *ctx, int enable, int reset, void *stream, double *ms_out, long *count_out, int nk);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *ctbop_last_error(void);
+
+/* Copy the lists of the last build to host memory, in user atom order, for
+ * tests: for every atom i its long-list (Coulomb, r < rc + skin) and
+ * short-list (covalent, r < S_ij + skin) neighbours as the user index j and
+ * the displacement vector x_j + n.h - x_i (at the positions of the last call).
+ * counts_*: int[n]; j_*: int[n*cap]; d_*: double[3*n*cap] (row i at i*cap). */
+int ctbop_debug_lists(ctbop_ctx *ctx, int n, void *sys_dev, size_t sys_bytes, int long_cap,
+                      int short_cap, int *counts_long, int *j_long, double *d_long,
+                      int *counts_short, int *j_short, double *d_short, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CTBOP_H */

@@ -1,0 +1,248 @@
+"""MI355X-native charge-transfer bond-order potential for Si-C.
+
+Thin Python binding of the C ABI in include/ctbop.h (libctbop.so, HIP for
+gfx950).  Every step of the energy/force/charge evaluation runs in the HIP
+kernels; this module only marshals arguments: torch tensors provide device
+memory and the current stream.  There is no CPU fallback: importing works on
+any machine, but every call needs the built library and a HIP device and
+raises otherwise.
+
+    pot = Potential(params)                       # flat 56-double parameter vector
+    E, F, q, info = pot.compute(pos, types, box, pbc)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libctbop.so")
+N_PARAMS = 56
+
+OK, E_INVAL, E_NOMEM, E_TOO_CLOSE, E_QEQ_NOCONV, E_QEQ_NOT_PD, E_NEIGH_OVERFLOW, E_HIP, E_BUSY = range(9)
+FLAG_WARM_START, FLAG_FORCE_REBUILD = 1, 2
+_CODES = {1: "E_INVAL", 2: "E_NOMEM", 3: "E_TOO_CLOSE", 4: "E_QEQ_NOCONV", 5: "E_QEQ_NOT_PD",
+          6: "E_NEIGH_OVERFLOW", 7: "E_HIP", 8: "E_BUSY"}
+
+
+class CtbopError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int), ("skin", ctypes.c_double),
+                ("long_cap", ctypes.c_int), ("short_cap", ctypes.c_int), ("fp64", ctypes.c_int),
+                ("cg_check", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("energy", ctypes.c_double), ("cg_residual", ctypes.c_double), ("mu", ctypes.c_double),
+                ("cg_iters", ctypes.c_int), ("rebuilt", ctypes.c_int), ("status", ctypes.c_int),
+                ("max_long", ctypes.c_int), ("max_short", ctypes.c_int),
+                ("nnz_long", ctypes.c_ulonglong), ("nnz_short", ctypes.c_ulonglong)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+EXPORTS = ("ctbop_default_opts", "ctbop_create", "ctbop_destroy", "ctbop_system_bytes",
+           "ctbop_compute_energy_forces_charges", "ctbop_md_run", "ctbop_status", "ctbop_last_error",
+           "ctbop_debug_lists", "ctbop_profile")
+
+
+def lib():
+    """Load libctbop.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m paper_1802_07871_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+        L.ctbop_default_opts.argtypes = [ctypes.POINTER(Opts)]
+        L.ctbop_create.argtypes = [vp, i32, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+        L.ctbop_destroy.argtypes = [vp]
+        L.ctbop_system_bytes.argtypes = [vp, i32, vp, vp, ctypes.POINTER(sz)]
+        L.ctbop_compute_energy_forces_charges.argtypes = [vp, i32, vp, vp, vp, vp, dbl, i32, vp, sz, vp, vp,
+                                                          vp, ctypes.POINTER(Info), vp]
+        L.ctbop_md_run.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, dbl, dbl, i32, i32, vp, sz, vp, vp, vp,
+                                   ctypes.POINTER(Info), vp]
+        L.ctbop_status.argtypes = [vp, vp, sz, vp, ctypes.POINTER(i32)]
+        L.ctbop_last_error.restype = ctypes.c_char_p
+        L.ctbop_debug_lists.argtypes = [vp, i32, vp, sz, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.ctbop_profile.argtypes = [vp, i32, i32, vp, vp, vp, i32]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise CtbopError(rc, lib().ctbop_last_error().decode())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the CTBOP library needs a HIP device; none is visible")
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _box_pbc(box, pbc):
+    b = np.ascontiguousarray(np.asarray(box, dtype=np.float64).reshape(9))
+    p = np.ascontiguousarray(np.asarray(pbc, dtype=bool).astype(np.int32).reshape(3))
+    return b, p
+
+
+class System:
+    """Caller-owned device buffer that carries one atomic system's lists,
+    sort order and warm-start charges between calls."""
+
+    def __init__(self, pot: "Potential", n: int, box, pbc):
+        torch = _torch()
+        b, p = _box_pbc(box, pbc)
+        nbytes = ctypes.c_size_t()
+        _check(lib().ctbop_system_bytes(pot.ctx, int(n), b.ctypes.data, p.ctypes.data, ctypes.byref(nbytes)))
+        self.nbytes = int(nbytes.value)
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device="cuda")
+        self.n = int(n)
+
+    def ptr(self):
+        return ctypes.c_void_p(self.buf.data_ptr())
+
+
+class Potential:
+    """A parameter set and solver options (a ctbop_ctx)."""
+
+    def __init__(self, params=None, cg_tol: float = 1e-9, cg_maxit: int = 500, skin: float = 0.5,
+                 long_cap: int = 512, short_cap: int = 64, fp64: bool = False, cg_check: int = 4):
+        if params is None:
+            from ctbop_inputs import params as _p
+            params = _p.load()
+        th = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+        if th.shape != (N_PARAMS,):
+            raise ValueError("expected 56 parameters")
+        self.params = th
+        self.opts = Opts(cg_tol, cg_maxit, skin, long_cap, short_cap, int(bool(fp64)), cg_check)
+        h = ctypes.c_void_p()
+        _check(lib().ctbop_create(th.ctypes.data, N_PARAMS, ctypes.byref(self.opts), ctypes.byref(h)))
+        self.ctx = h
+        self._systems: dict = {}
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None) and _lib is not None:
+                _lib.ctbop_destroy(self.ctx)
+        except Exception:
+            pass
+
+    def system(self, n, box, pbc) -> System:
+        return System(self, n, box, pbc)
+
+    def _sys_for(self, n, box, pbc, sysbuf):
+        if sysbuf is not None:
+            return sysbuf
+        key = (int(n), tuple(np.asarray(box, dtype=np.float64).ravel()), tuple(np.asarray(pbc, dtype=bool)))
+        s = self._systems.get(key)
+        if s is None:
+            s = self._systems[key] = System(self, n, box, pbc)
+        return s
+
+    def compute_soa(self, pos_soa, types, box, pbc, Q=0.0, warm=True, force_rebuild=False,
+                    sysbuf: System | None = None, E=None, F=None, q=None, want_info=True):
+        """Device-array form: pos_soa (3n,) float64 CUDA tensor (x.., y.., z..),
+        types (n,) int32 CUDA tensor.  Returns (E[1], F_soa[3n], q[n], info|None)."""
+        torch = _torch()
+        n = types.shape[0]
+        assert pos_soa.dtype == torch.float64 and pos_soa.is_cuda and pos_soa.is_contiguous()
+        assert pos_soa.numel() == 3 * n and types.dtype == torch.int32 and types.is_cuda
+        s = self._sys_for(n, box, pbc, sysbuf)
+        b, p = _box_pbc(box, pbc)
+        E = torch.empty(1, dtype=torch.float64, device="cuda") if E is None else E
+        F = torch.empty(3 * n, dtype=torch.float64, device="cuda") if F is None else F
+        q = torch.empty(n, dtype=torch.float64, device="cuda") if q is None else q
+        info = Info() if want_info else None
+        flags = (FLAG_WARM_START if warm else 0) | (FLAG_FORCE_REBUILD if force_rebuild else 0)
+        rc = lib().ctbop_compute_energy_forces_charges(
+            self.ctx, int(n), ctypes.c_void_p(pos_soa.data_ptr()), ctypes.c_void_p(types.data_ptr()),
+            b.ctypes.data, p.ctypes.data, float(Q), flags, s.ptr(), s.nbytes, ctypes.c_void_p(E.data_ptr()),
+            ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(q.data_ptr()),
+            ctypes.byref(info) if info is not None else None, _stream())
+        _check(rc)
+        return E, F, q, (info.as_dict() if info is not None else None)
+
+    def compute(self, pos, types, box, pbc, Q=0.0, warm=True, force_rebuild=False, sysbuf=None):
+        """pos (n,3) and types (n,) as numpy arrays or tensors.  Returns
+        (E float, F (n,3) float64 tensor, q (n,) tensor, info dict)."""
+        torch = _torch()
+        pos = torch.as_tensor(pos, dtype=torch.float64, device="cuda").reshape(-1, 3)
+        types = torch.as_tensor(types, dtype=torch.int32, device="cuda").contiguous()
+        pos_soa = pos.t().contiguous().reshape(-1)
+        E, F, q, info = self.compute_soa(pos_soa, types, box, pbc, Q, warm, force_rebuild, sysbuf)
+        n = types.shape[0]
+        return float(E.item()), F.reshape(3, n).t().contiguous(), q, info
+
+    def md_run(self, pos, vel, types, box, pbc, dt, nsteps, fixed=None, Q=0.0, thermo_every=1,
+               sysbuf=None):
+        """Velocity-Verlet NVE on the device.  pos, vel (n,3).  Returns
+        (pos (n,3), vel (n,3), F (n,3), q (n,), thermo (k,2) numpy [Epot, Ekin], info)."""
+        torch = _torch()
+        pos = torch.as_tensor(pos, dtype=torch.float64, device="cuda").reshape(-1, 3)
+        vel = torch.as_tensor(vel, dtype=torch.float64, device="cuda").reshape(-1, 3)
+        types = torch.as_tensor(types, dtype=torch.int32, device="cuda").contiguous()
+        n = types.shape[0]
+        x = pos.t().contiguous().reshape(-1)
+        v = vel.t().contiguous().reshape(-1)
+        F = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+        q = torch.empty(n, dtype=torch.float64, device="cuda")
+        fx = None
+        if fixed is not None:
+            fx = torch.as_tensor(np.asarray(fixed, dtype=np.uint8), device="cuda").contiguous()
+        s = self._sys_for(n, box, pbc, sysbuf)
+        b, p = _box_pbc(box, pbc)
+        every = max(1, int(thermo_every))
+        thermo = np.zeros((nsteps // every + 1, 2))
+        info = Info()
+        rc = lib().ctbop_md_run(self.ctx, int(n), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(v.data_ptr()),
+                                ctypes.c_void_p(types.data_ptr()),
+                                ctypes.c_void_p(fx.data_ptr()) if fx is not None else None,
+                                b.ctypes.data, p.ctypes.data, float(Q), float(dt), int(nsteps), every,
+                                s.ptr(), s.nbytes, ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(q.data_ptr()),
+                                thermo.ctypes.data, ctypes.byref(info), _stream())
+        _check(rc)
+        return (x.reshape(3, n).t().contiguous(), v.reshape(3, n).t().contiguous(),
+                F.reshape(3, n).t().contiguous(), q, thermo, info.as_dict())
+
+    KERNELS = ("spmv", "force_coul", "assemble", "bond", "force_cov", "cg_update", "cg_dir", "build")
+
+    def profile(self, enable=True, reset=True):
+        """Per-kernel event timing: returns {name: (ms_total, launches)} accumulated
+        so far, then sets timing on/off (and clears the totals if reset)."""
+        ms = np.zeros(16)
+        cnt = np.zeros(16, dtype=np.int64)
+        _check(lib().ctbop_profile(self.ctx, int(enable), int(reset), _stream(), ms.ctypes.data,
+                                   cnt.ctypes.data, 16))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.KERNELS)}
+
+    def debug_lists(self, sysbuf: System, long_cap=None, short_cap=None):
+        """Lists of the last build as numpy (counts, j, d) for long and short."""
+        n = sysbuf.n
+        lc = long_cap or self.opts.long_cap
+        sc = short_cap or self.opts.short_cap
+        cl = np.zeros(n, np.int32)
+        jl = np.zeros(n * lc, np.int32)
+        dl = np.zeros(3 * n * lc)
+        cs = np.zeros(n, np.int32)
+        js = np.zeros(n * sc, np.int32)
+        ds = np.zeros(3 * n * sc)
+        _check(lib().ctbop_debug_lists(self.ctx, n, sysbuf.ptr(), sysbuf.nbytes, lc, sc, cl.ctypes.data,
+                                       jl.ctypes.data, dl.ctypes.data, cs.ctypes.data, js.ctypes.data,
+                                       ds.ctypes.data, _stream()))
+        return (cl, jl.reshape(n, lc), dl.reshape(n, lc, 3)), (cs, js.reshape(n, sc), ds.reshape(n, sc, 3))

@@ -1,0 +1,722 @@
+// ctbop.hip -- host side of the C ABI (include/ctbop.h): contexts, layout of
+// the caller-owned per-system buffer, and the launch sequence of one
+// energy/force/charge evaluation and of the MD loop.  All device work is in
+// the kernels included below; this file only validates, lays out memory and
+// launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/ctbop.h"
+#include "ctbop_dev.h"
+#include "k_lists.h"
+#include "k_tersoff.h"
+#include "k_qeq.h"
+#include "k_md.h"
+
+using namespace ctbop;
+
+namespace {
+
+constexpr int LPR = 16;             // lanes per Coulomb-list row
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) return fail(CTBOP_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct Sig {
+    int n;
+    double box[9];
+    int pbc[3];
+    int fp64;
+    size_t bytes;
+    bool operator==(const Sig &o) const
+    {
+        return n == o.n && fp64 == o.fp64 && bytes == o.bytes && !memcmp(box, o.box, sizeof box) &&
+               !memcmp(pbc, o.pbc, sizeof pbc);
+    }
+};
+
+struct Layout {
+    Seg seg;               // with device addresses filled in
+    size_t off_seg, off_sst, off_tiles, off_segid, off_ke;
+    size_t bytes;
+    int ntile;
+};
+
+} // namespace
+
+struct ctbop_ctx {
+    double theta[CTBOP_N_PARAMS];
+    ctbop_opts opts;
+    Params<float> pf;
+    Params<double> pd;
+    std::unordered_map<void *, Sig> seen;
+    std::unordered_map<void *, int> last_iters;
+    int *host_flag = nullptr;    // pinned: done, iters
+    // optional per-kernel timing with HIP events on the caller's stream
+    int profile = 0;
+    std::vector<hipEvent_t> ev_free;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+    double prof_ms[16] = {0};
+    long prof_n[16] = {0};
+};
+
+namespace {
+
+template <typename R>
+void fill_params(const double *t, const ctbop_opts &o, Params<R> &P)
+{
+    memset(&P, 0, sizeof P);
+    const double *s[2] = {t, t + 26};
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++) {
+            int pp = a * 2 + b;
+            P.A[pp] = (R)std::sqrt(s[a][0] * s[b][0]);
+            P.B[pp] = (R)(std::sqrt(s[a][1] * s[b][1]) * (a != b ? t[52] : 1.0));
+            P.lam1[pp] = (R)(0.5 * (s[a][2] + s[b][2]));
+            P.lam2[pp] = (R)(0.5 * (s[a][3] + s[b][3]));
+            double Rc = std::sqrt(s[a][4] * s[b][4]), Sc = std::sqrt(s[a][5] * s[b][5]);
+            P.Rc[pp] = (R)Rc;
+            P.Sc[pp] = (R)Sc;
+            P.piSR[pp] = (R)(M_PI / (Sc - Rc));
+            P.g3[pp] = (R)std::pow(s[a][23] * s[b][23], -1.5);
+            P.s_cut2[pp] = (float)((Sc + o.skin) * (Sc + o.skin));
+        }
+    const double p = t[55];
+    for (int a = 0; a < 2; a++) {
+        const double *c = s[a];
+        double sig = c[6];
+        double g1 = c[7 + 5], g2 = c[14 + 5];
+        P.G[a] = (R)std::pow(std::pow(g1, -p) + std::pow(g2, -p), -1.0 / (2.0 * sig * p));
+        P.inv2sig[a] = (R)(1.0 / (2.0 * sig));
+        for (int l = 0; l < 2; l++) {
+            const double *ch = c + 7 + 7 * l;
+            P.gam[a][l] = (R)ch[0];
+            P.c2[a][l] = (R)(ch[1] * ch[1]);
+            P.d2[a][l] = (R)(ch[2] * ch[2]);
+            P.h[a][l] = (R)ch[3];
+            P.nn[a][l] = (R)ch[4];
+            P.g[a][l] = (R)ch[5];
+            P.alpha[a][l] = (R)ch[6];
+        }
+        P.alpha_zero[a] = (c[7 + 6] == 0.0 && c[14 + 6] == 0.0) ? 1 : 0;
+        P.chi[a] = c[21];
+        P.J[a] = c[22];
+        P.E0[a] = c[24];
+        P.mass[a] = c[25];
+    }
+    P.p = (R)p;
+    P.p_is_2 = (p == 2.0) ? 1 : 0;
+    P.ke = (R)t[53];
+    P.rc = (R)t[54];
+    P.inv_rc = (R)(1.0 / t[54]);
+    P.l_cut2 = (float)((t[54] + o.skin) * (t[54] + o.skin));
+    P.close2 = 0.25f;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Geometry of the cell grid and the byte layout of the per-system buffer.
+int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, char *base, Layout &L)
+{
+    if (n <= 0 || n > MAX_ATOMS) return fail(CTBOP_E_INVAL, "atom count out of range");
+    Seg &S = L.seg;
+    memset(&S, 0, sizeof S);
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) S.h[a][b] = box[3 * a + b];
+    const double(*h)[3] = S.h;
+    double det = h[0][0] * (h[1][1] * h[2][2] - h[1][2] * h[2][1]) - h[0][1] * (h[1][0] * h[2][2] - h[1][2] * h[2][0]) +
+                 h[0][2] * (h[1][0] * h[2][1] - h[1][1] * h[2][0]);
+    if (!(det > 0.0)) return fail(CTBOP_E_INVAL, "box must be right-handed with positive volume");
+    S.hi[0][0] = (h[1][1] * h[2][2] - h[1][2] * h[2][1]) / det;
+    S.hi[0][1] = (h[0][2] * h[2][1] - h[0][1] * h[2][2]) / det;
+    S.hi[0][2] = (h[0][1] * h[1][2] - h[0][2] * h[1][1]) / det;
+    S.hi[1][0] = (h[1][2] * h[2][0] - h[1][0] * h[2][2]) / det;
+    S.hi[1][1] = (h[0][0] * h[2][2] - h[0][2] * h[2][0]) / det;
+    S.hi[1][2] = (h[0][2] * h[1][0] - h[0][0] * h[1][2]) / det;
+    S.hi[2][0] = (h[1][0] * h[2][1] - h[1][1] * h[2][0]) / det;
+    S.hi[2][1] = (h[0][1] * h[2][0] - h[0][0] * h[2][1]) / det;
+    S.hi[2][2] = (h[0][0] * h[1][1] - h[0][1] * h[1][0]) / det;
+    const double rl = ctx->theta[54] + ctx->opts.skin;
+    double w[3];
+    for (int a = 0; a < 3; a++) {
+        const double *u = h[(a + 1) % 3], *v = h[(a + 2) % 3];
+        double cx = u[1] * v[2] - u[2] * v[1], cy = u[2] * v[0] - u[0] * v[2], cz = u[0] * v[1] - u[1] * v[0];
+        w[a] = det / std::sqrt(cx * cx + cy * cy + cz * cz);
+        S.pbc[a] = pbc[a] ? 1 : 0;
+        S.nb[a] = std::max(1, (int)std::floor(w[a] / (0.5 * rl)));
+    }
+    // keep the grid at most a few cells per atom (huge vacuum boxes)
+    const long cap = std::max<long>(4096, 8L * n);
+    while ((long)S.nb[0] * S.nb[1] * S.nb[2] > cap) {
+        int a = (S.nb[0] >= S.nb[1] && S.nb[0] >= S.nb[2]) ? 0 : (S.nb[1] >= S.nb[2] ? 1 : 2);
+        S.nb[a] = std::max(1, S.nb[a] / 2);
+    }
+    for (int a = 0; a < 3; a++) {
+        int st = (int)std::ceil(rl * S.nb[a] / w[a] - 1e-12);
+        if (S.pbc[a]) {
+            if (st > 3) return fail(CTBOP_E_INVAL, "periodic cell narrower than (rc_coul + skin)/3");
+        } else {
+            st = std::min(st, S.nb[a] - 1);
+        }
+        S.st[a] = st;
+        for (int b = 0; b < 3; b++) S.cw[a][b] = h[a][b] / S.nb[a];
+    }
+    S.ncell = S.nb[0] * S.nb[1] * S.nb[2];
+    S.n = n;
+    S.npad = (n + TILE - 1) / TILE * TILE;
+    S.ntile = S.npad / TILE;
+    S.tile0 = 0;
+    S.Wl = ctx->opts.long_cap;
+    S.Ws = ctx->opts.short_cap;
+    S.skin = ctx->opts.skin;
+    const int fp64 = ctx->opts.fp64;
+    const size_t rsz = fp64 ? 8 : 4, v4 = fp64 ? 32 : 16;
+    const size_t np = S.npad;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes, 256);
+        return at;
+    };
+    L.off_seg = take(sizeof(Seg));
+    L.off_sst = take(sizeof(SegState));
+    L.off_tiles = take(sizeof(Tile) * S.ntile);
+    L.off_segid = take(sizeof(int));
+    L.off_ke = take(2 * sizeof(double));
+    size_t o_perm = take(4 * np), o_cellof = take(4 * (size_t)n), o_csort = take(4 * np);
+    size_t o_cs = take(4 * ((size_t)S.ncell + 1)), o_cc = take(4 * (size_t)S.ncell);
+    size_t o_off = take(8 * 3 * np), o_ref = take(8 * 3 * (size_t)n), o_xs = take(v4 * np);
+    size_t o_xs64 = fp64 ? o_xs : take(32 * np);
+    size_t o_lcnt = take(4 * np), o_lidx = take(4 * np * S.Wl), o_H = take(rsz * np * S.Wl);
+    size_t o_scnt = take(4 * np), o_sidx = take(4 * np * S.Ws), o_srev = take(np * S.Ws), o_slot = take(v4 * np * S.Ws);
+    size_t o_ecov = take(8 * np), o_fcov = take(8 * 3 * np);
+    size_t o_q = take(8 * np), o_r = take(8 * np), o_p = take(8 * np), o_s = take(8 * np), o_d = take(8 * np),
+           o_jd = take(8 * np);
+    size_t o_qs = take(8 * (size_t)n), o_part = take(8 * NPART * (size_t)S.ntile);
+    L.bytes = o;
+    L.ntile = S.ntile;
+    if (base) {
+        S.perm = (int *)(base + o_perm);
+        S.cell_of = (int *)(base + o_cellof);
+        S.csort = (int *)(base + o_csort);
+        S.cell_start = (int *)(base + o_cs);
+        S.cell_cnt = (int *)(base + o_cc);
+        S.off = (double *)(base + o_off);
+        S.ref_x = (double *)(base + o_ref);
+        S.xs = base + o_xs;
+        S.xs64 = (double4 *)(base + o_xs64);
+        S.lcnt = (int *)(base + o_lcnt);
+        S.lidx = (uint32_t *)(base + o_lidx);
+        S.H = base + o_H;
+        S.scnt = (int *)(base + o_scnt);
+        S.sidx = (uint32_t *)(base + o_sidx);
+        S.srev = (uint8_t *)(base + o_srev);
+        S.slot = base + o_slot;
+        S.ecov = (double *)(base + o_ecov);
+        S.Fcov = (double *)(base + o_fcov);
+        S.q = (double *)(base + o_q);
+        S.r = (double *)(base + o_r);
+        S.p = (double *)(base + o_p);
+        S.s = (double *)(base + o_s);
+        S.dinv = (double *)(base + o_d);
+        S.jd = (double *)(base + o_jd);
+        S.q_state = (double *)(base + o_qs);
+        S.part = (double *)(base + o_part);
+        S.sst = (SegState *)(base + L.off_sst);
+    }
+    return CTBOP_OK;
+}
+
+__global__ void k_reset_state(SegState *st, Tile *tiles, int ntile, int *segid)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        memset(st, 0, sizeof(SegState));
+        *segid = 0;
+    }
+    if (t < ntile) {
+        tiles[t].seg = 0;
+        tiles[t].row0 = t * TILE;
+    }
+}
+
+hipEvent_t ev_get(ctbop_ctx *ctx)
+{
+    if (ctx->ev_free.empty()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    hipEvent_t e = ctx->ev_free.back();
+    ctx->ev_free.pop_back();
+    return e;
+}
+
+// Launch wrapper: with profiling on, bracket the launch with events
+// (kernel class k) on the same stream.
+struct Timed {
+    ctbop_ctx *ctx;
+    int k;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    Timed(ctbop_ctx *c, int kk, hipStream_t s) : ctx(c), k(kk), st(s)
+    {
+        if (ctx->profile) {
+            a = ev_get(ctx);
+            if (a) (void)hipEventRecord(a, st);
+        }
+    }
+    ~Timed()
+    {
+        if (a) {
+            hipEvent_t b = ev_get(ctx);
+            if (b) {
+                (void)hipEventRecord(b, st);
+                ctx->ev_pending.push_back({k, {a, b}});
+            }
+        }
+    }
+};
+
+// after a stream synchronisation: fold completed event pairs into totals
+void ev_harvest(ctbop_ctx *ctx)
+{
+    for (auto &p : ctx->ev_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+            ctx->prof_ms[p.first] += ms;
+            ctx->prof_n[p.first] += 1;
+        }
+        ctx->ev_free.push_back(p.second.first);
+        ctx->ev_free.push_back(p.second.second);
+    }
+    ctx->ev_pending.clear();
+}
+
+int map_status(int st)
+{
+    if (st & ST_TOO_CLOSE) return CTBOP_E_TOO_CLOSE;
+    if (st & ST_OVERFLOW) return CTBOP_E_NEIGH_OVERFLOW;
+    if (st & ST_REV) return CTBOP_E_NEIGH_OVERFLOW;
+    if (st & ST_NOT_PD) return CTBOP_E_QEQ_NOT_PD;
+    if (st & ST_NOCONV) return CTBOP_E_QEQ_NOCONV;
+    return CTBOP_OK;
+}
+
+std::string status_text(int st)
+{
+    std::string s;
+    if (st & ST_TOO_CLOSE) s += "atoms closer than 0.5 A; ";
+    if (st & ST_OVERFLOW) s += "neighbour list overflow (raise long_cap/short_cap); ";
+    if (st & ST_REV) s += "covalent list not symmetric; ";
+    if (st & ST_NOT_PD) s += "charge matrix not positive definite; ";
+    if (st & ST_NOCONV) s += "charge solve did not converge; ";
+    return s;
+}
+
+struct Prep {
+    Layout L;
+    char *base;
+    Seg *dseg;
+    Tile *dtiles;
+    int *dsegid;
+    double *dke;
+    hipStream_t st;
+    bool fresh;
+};
+
+// validate, lay out, and (re)initialise the system buffer when it is new to
+// this context or its geometry changed
+int prepare(ctbop_ctx *ctx, int n, const double *box, const int *pbc, void *sys, size_t sys_bytes, void *stream,
+            Prep &P)
+{
+    if (!ctx || !box || !pbc || !sys) return fail(CTBOP_E_INVAL, "null argument");
+    P.base = (char *)sys;
+    int rc = make_layout(ctx, n, box, pbc, P.base, P.L);
+    if (rc) return rc;
+    if (sys_bytes < P.L.bytes) return fail(CTBOP_E_NOMEM, "system buffer smaller than ctbop_system_bytes()");
+    P.dseg = (Seg *)(P.base + P.L.off_seg);
+    P.dtiles = (Tile *)(P.base + P.L.off_tiles);
+    P.dsegid = (int *)(P.base + P.L.off_segid);
+    P.dke = (double *)(P.base + P.L.off_ke);
+    P.st = (hipStream_t)stream;
+    Sig sig;
+    memset(&sig, 0, sizeof sig);
+    sig.n = n;
+    memcpy(sig.box, box, sizeof sig.box);
+    for (int a = 0; a < 3; a++) sig.pbc[a] = pbc[a] ? 1 : 0;
+    sig.fp64 = ctx->opts.fp64;
+    sig.bytes = P.L.bytes;
+    auto it = ctx->seen.find(sys);
+    P.fresh = (it == ctx->seen.end() || !(it->second == sig));
+    if (!ctx->host_flag) HIPCHK(hipHostMalloc((void **)&ctx->host_flag, 64, hipHostMallocDefault));
+    if (P.fresh) {
+        hipLaunchKernelGGL(k_reset_state, dim3((P.L.ntile + 255) / 256), dim3(256), 0, P.st, P.L.seg.sst, P.dtiles,
+                           P.L.ntile, P.dsegid);
+        HIPCHK(hipGetLastError());
+        ctx->seen[sys] = sig;
+        ctx->last_iters[sys] = 0;
+    }
+    return CTBOP_OK;
+}
+
+template <typename R>
+int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *iters_out)
+{
+    const int nt = P.L.ntile;
+    const dim3 g(nt), b(TILE);
+    hipStream_t st = P.st;
+    const int force = (flags & CTBOP_FLAG_FORCE_REBUILD) || P.fresh;
+    const int warm = (flags & CTBOP_FLAG_WARM_START) && !P.fresh;
+    hipLaunchKernelGGL(k_call_init, dim3(1), dim3(64), 0, st, P.dseg, 1, force);
+    hipLaunchKernelGGL(k_check_disp, g, b, 0, st, P.dtiles, P.dseg);
+    hipLaunchKernelGGL(k_bin_clear, g, b, 0, st, P.dtiles, P.dseg);
+    hipLaunchKernelGGL(k_bin, g, b, 0, st, P.dtiles, P.dseg);
+    hipLaunchKernelGGL(k_scan, dim3(1), b, 0, st, P.dsegid, P.dseg);
+    hipLaunchKernelGGL(k_scatter, g, b, 0, st, P.dtiles, P.dseg);
+    hipLaunchKernelGGL(k_cell_sort, g, b, 0, st, P.dtiles, P.dseg);
+    hipLaunchKernelGGL(k_gather<R>, g, b, 0, st, P.dtiles, P.dseg, warm);
+    hipLaunchKernelGGL(k_qfix, g, b, 0, st, P.dtiles, P.dseg);
+    {
+        Timed t(ctx, 7, st);
+        hipLaunchKernelGGL(k_build<R>, g, b, 0, st, P.dtiles, P.dseg, prm);
+    }
+    hipLaunchKernelGGL(k_rev, g, b, 0, st, P.dtiles, P.dseg);
+    hipLaunchKernelGGL(k_mark_built, dim3(1), dim3(64), 0, st, P.dseg, 1);
+    {
+        Timed t(ctx, 3, st);
+        hipLaunchKernelGGL((k_bond<R>), g, b, 0, st, P.dtiles, P.dseg, prm, ctx->pd);
+    }
+    CgCtl ctl{ctx->opts.cg_tol, ctx->opts.cg_maxit};
+    {
+        Timed t(ctx, 2, st);
+        hipLaunchKernelGGL((k_assemble<R, LPR>), g, b, 0, st, P.dtiles, P.dseg, prm, ctx->pd, ctl);
+    }
+    HIPCHK(hipGetLastError());
+    // charge solve: launch iterations in chunks, then read the convergence flag
+    int done_it = 0;
+    int chunk = std::max(ctx->opts.cg_check, std::min(ctx->last_iters[P.base], ctx->opts.cg_maxit));
+    for (;;) {
+        for (int c = 0; c < chunk; c++) {
+            {
+                Timed t(ctx, 6, st);
+                hipLaunchKernelGGL(k_cg_dir, g, b, 0, st, P.dtiles, P.dseg);
+            }
+            {
+                Timed t(ctx, 0, st);
+                hipLaunchKernelGGL((k_spmv<R, LPR>), g, b, 0, st, P.dtiles, P.dseg, prm);
+            }
+            {
+                Timed t(ctx, 5, st);
+                hipLaunchKernelGGL(k_cg_update, g, b, 0, st, P.dtiles, P.dseg, ctl);
+            }
+        }
+        done_it += chunk;
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(ctx->host_flag, &P.L.seg.sst->done, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (ctx->profile) ev_harvest(ctx);
+        if (ctx->host_flag[0] || done_it >= ctx->opts.cg_maxit + 1) break;
+        chunk = ctx->opts.cg_check;
+    }
+    ctx->last_iters[P.base] = ctx->host_flag[1];
+    if (iters_out) *iters_out = ctx->host_flag[1];
+    {
+        Timed t(ctx, 4, st);
+        hipLaunchKernelGGL((k_force_cov<R>), g, b, 0, st, P.dtiles, P.dseg, prm);
+    }
+    {
+        Timed t(ctx, 1, st);
+        hipLaunchKernelGGL((k_force_coul<R, LPR>), g, b, 0, st, P.dtiles, P.dseg, prm, ctx->pd);
+    }
+    HIPCHK(hipGetLastError());
+    return CTBOP_OK;
+}
+
+int eval_any(ctbop_ctx *ctx, Prep &P, int flags, int *iters)
+{
+    if (ctx->opts.fp64) return launch_eval<double>(ctx, P, ctx->pd, flags, iters);
+    return launch_eval<float>(ctx, P, ctx->pf, flags, iters);
+}
+
+int fill_info(ctbop_ctx *ctx, Prep &P, ctbop_info *info)
+{
+    SegState ss;
+    HIPCHK(hipMemcpyAsync(&ss, P.L.seg.sst, sizeof ss, hipMemcpyDeviceToHost, P.st));
+    HIPCHK(hipStreamSynchronize(P.st));
+    if (ctx->profile) ev_harvest(ctx);
+    info->energy = ss.energy;
+    info->cg_residual = ss.res;
+    info->mu = ss.mu_prev;
+    info->cg_iters = ss.iters;
+    info->rebuilt = ss.rebuild;
+    info->status = map_status(ss.status);
+    info->max_long = ss.maxl;
+    info->max_short = ss.maxs;
+    info->nnz_long = ss.nnz_long;
+    info->nnz_short = ss.nnz_short;
+    if (ss.status) return fail(info->status, status_text(ss.status));
+    return CTBOP_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+void ctbop_default_opts(ctbop_opts *o)
+{
+    o->cg_tol = 1e-9;
+    o->cg_maxit = 500;
+    o->skin = 0.5;
+    o->long_cap = 512;
+    o->short_cap = 64;
+    o->fp64 = 0;
+    o->cg_check = 4;
+}
+
+int ctbop_create(const double *params, int n_params, const ctbop_opts *opts, ctbop_ctx **out)
+{
+    if (!params || !out) return fail(CTBOP_E_INVAL, "null argument");
+    if (n_params != CTBOP_N_PARAMS) return fail(CTBOP_E_INVAL, "expected 56 parameters");
+    for (int t = 0; t < 2; t++) {
+        const double *s = params + 26 * t;
+        if (!(s[6] > 0) || !(s[11] > 0) || !(s[18] > 0) || !(s[12] > 0) || !(s[19] > 0) || !(s[22] > 0) ||
+            !(s[5] > s[4]) || !(s[23] > 0))
+            return fail(CTBOP_E_INVAL, "parameters: need sigma, n_l, g_l, J, gamma_coul > 0 and S > R");
+    }
+    if (!(params[55] > 0) || !(params[54] > 0)) return fail(CTBOP_E_INVAL, "parameters: need p > 0, rc > 0");
+    ctbop_ctx *c = new ctbop_ctx();
+    memcpy(c->theta, params, sizeof c->theta);
+    ctbop_default_opts(&c->opts);
+    if (opts) {
+        c->opts = *opts;
+        ctbop_opts d;
+        ctbop_default_opts(&d);
+        if (c->opts.cg_tol <= 0) c->opts.cg_tol = d.cg_tol;
+        if (c->opts.cg_maxit <= 0) c->opts.cg_maxit = d.cg_maxit;
+        if (c->opts.skin < 0) c->opts.skin = d.skin;
+        if (c->opts.long_cap <= 0) c->opts.long_cap = d.long_cap;
+        if (c->opts.short_cap <= 0) c->opts.short_cap = d.short_cap;
+        if (c->opts.cg_check <= 0) c->opts.cg_check = d.cg_check;
+    }
+    if (c->opts.short_cap > 255) {
+        delete c;
+        return fail(CTBOP_E_INVAL, "short_cap must be <= 255");
+    }
+    fill_params<float>(c->theta, c->opts, c->pf);
+    fill_params<double>(c->theta, c->opts, c->pd);
+    *out = c;
+    return CTBOP_OK;
+}
+
+int ctbop_destroy(ctbop_ctx *ctx)
+{
+    if (!ctx) return CTBOP_OK;
+    if (ctx->host_flag) (void)hipHostFree(ctx->host_flag);
+    for (auto e : ctx->ev_free) (void)hipEventDestroy(e);
+    for (auto &p : ctx->ev_pending) {
+        (void)hipEventDestroy(p.second.first);
+        (void)hipEventDestroy(p.second.second);
+    }
+    delete ctx;
+    return CTBOP_OK;
+}
+
+int ctbop_system_bytes(ctbop_ctx *ctx, int n, const double *box, const int *pbc, size_t *bytes)
+{
+    if (!ctx || !box || !pbc || !bytes) return fail(CTBOP_E_INVAL, "null argument");
+    Layout L;
+    int rc = make_layout(ctx, n, box, pbc, nullptr, L);
+    if (rc) return rc;
+    *bytes = L.bytes;
+    return CTBOP_OK;
+}
+
+int ctbop_compute_energy_forces_charges(ctbop_ctx *ctx, int n, const double *pos, const int32_t *types,
+                                        const double *box, const int *pbc, double Q, int flags, void *sys,
+                                        size_t sys_bytes, double *E, double *F, double *q, ctbop_info *info,
+                                        void *stream)
+{
+    if (!pos || !types || !F || !q) return fail(CTBOP_E_INVAL, "null array argument");
+    Prep P;
+    int rc = prepare(ctx, n, box, pbc, sys, sys_bytes, stream, P);
+    if (rc) return rc;
+    Seg S = P.L.seg;
+    S.x = pos;
+    S.type = types;
+    S.F = F;
+    S.q_out = q;
+    S.E_out = E;
+    S.Q = Q;
+    hipLaunchKernelGGL(k_set_seg, dim3(1), dim3(1), 0, P.st, P.dseg, S);
+    int iters = 0;
+    rc = eval_any(ctx, P, flags, &iters);
+    if (rc) return rc;
+    if (info) return fill_info(ctx, P, info);
+    return CTBOP_OK;
+}
+
+int ctbop_md_run(ctbop_ctx *ctx, int n, double *x, double *v, const int32_t *types, const uint8_t *fixed,
+                 const double *box, const int *pbc, double Q, double dt, int nsteps, int every, void *sys,
+                 size_t sys_bytes, double *F, double *q, double *thermo, ctbop_info *info, void *stream)
+{
+    if (!x || !v || !types || !F || !q || nsteps < 0) return fail(CTBOP_E_INVAL, "bad argument");
+    if (every <= 0) every = 1;
+    Prep P;
+    int rc = prepare(ctx, n, box, pbc, sys, sys_bytes, stream, P);
+    if (rc) return rc;
+    Seg S = P.L.seg;
+    S.x = x;
+    S.type = types;
+    S.F = F;
+    S.q_out = q;
+    S.E_out = nullptr;
+    S.Q = Q;
+    hipLaunchKernelGGL(k_set_seg, dim3(1), dim3(1), 0, P.st, P.dseg, S);
+    MdIO io;
+    io.x = x;
+    io.v = v;
+    io.F = F;
+    io.fixed = fixed;
+    io.dt = dt;
+    io.mass[0] = ctx->theta[25];
+    io.mass[1] = ctx->theta[26 + 25];
+    const dim3 g(P.L.ntile), b(TILE);
+    int iters = 0, status_acc = 0;
+    // forces at the start
+    rc = eval_any(ctx, P, CTBOP_FLAG_WARM_START, &iters);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_md_kick, g, b, 0, P.st, P.dtiles, P.dseg, MdIO{x, v, F, fixed, 0.0, {io.mass[0], io.mass[1]}}, P.dke);
+    for (int s = 0; s <= nsteps; s++) {
+        if (s > 0) {
+            hipLaunchKernelGGL(k_md_kick_drift, g, b, 0, P.st, P.dtiles, P.dseg, io);
+            rc = eval_any(ctx, P, CTBOP_FLAG_WARM_START, &iters);
+            if (rc) return rc;
+            hipLaunchKernelGGL(k_md_kick, g, b, 0, P.st, P.dtiles, P.dseg, io, P.dke);
+            HIPCHK(hipGetLastError());
+        }
+        if (thermo && s % every == 0) {
+            double kv[2];
+            HIPCHK(hipMemcpyAsync(kv, P.dke, sizeof kv, hipMemcpyDeviceToHost, P.st));
+            HIPCHK(hipStreamSynchronize(P.st));
+            thermo[2 * (s / every)] = kv[1];
+            thermo[2 * (s / every) + 1] = kv[0];
+        }
+        if (s % 64 == 0 || s == nsteps) {
+            int code = 0;
+            HIPCHK(hipMemcpyAsync(&code, &P.L.seg.sst->status, sizeof(int), hipMemcpyDeviceToHost, P.st));
+            HIPCHK(hipStreamSynchronize(P.st));
+            status_acc |= code;
+            if (code) return fail(map_status(code), status_text(code));
+        }
+    }
+    (void)status_acc;
+    if (info) return fill_info(ctx, P, info);
+    HIPCHK(hipStreamSynchronize(P.st));
+    return CTBOP_OK;
+}
+
+int ctbop_status(ctbop_ctx *ctx, void *sys, size_t sys_bytes, void *stream, int *code)
+{
+    if (!ctx || !sys || !code) return fail(CTBOP_E_INVAL, "null argument");
+    auto it = ctx->seen.find(sys);
+    if (it == ctx->seen.end()) return fail(CTBOP_E_INVAL, "system buffer not used with this context");
+    Layout L;
+    int rc = make_layout(ctx, it->second.n, it->second.box, it->second.pbc, (char *)sys, L);
+    if (rc) return rc;
+    if (sys_bytes < L.bytes) return fail(CTBOP_E_NOMEM, "system buffer too small");
+    int st = 0;
+    HIPCHK(hipMemcpyAsync(&st, &L.seg.sst->status, sizeof(int), hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    *code = map_status(st);
+    return CTBOP_OK;
+}
+
+const char *ctbop_last_error(void) { return g_err.c_str(); }
+
+int ctbop_profile(ctbop_ctx *ctx, int enable, int reset, void *stream, double *ms_out, long *count_out, int nk)
+{
+    if (!ctx) return fail(CTBOP_E_INVAL, "null context");
+    if (stream || !ctx->ev_pending.empty()) {
+        HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+        ev_harvest(ctx);
+    }
+    for (int k = 0; k < nk && k < 16; k++) {
+        if (ms_out) ms_out[k] = ctx->prof_ms[k];
+        if (count_out) count_out[k] = ctx->prof_n[k];
+    }
+    if (reset)
+        for (int k = 0; k < 16; k++) {
+            ctx->prof_ms[k] = 0.0;
+            ctx->prof_n[k] = 0;
+        }
+    ctx->profile = enable ? 1 : 0;
+    return CTBOP_OK;
+}
+
+int ctbop_debug_lists(ctbop_ctx *ctx, int n, void *sys, size_t sys_bytes, int long_cap, int short_cap,
+                      int *cl, int *jl, double *dl, int *cs, int *js, double *ds, void *stream)
+{
+    if (!ctx || !sys) return fail(CTBOP_E_INVAL, "null argument");
+    auto it = ctx->seen.find(sys);
+    if (it == ctx->seen.end() || it->second.n != n) return fail(CTBOP_E_INVAL, "system buffer not set up for n atoms");
+    Layout L;
+    int rc = make_layout(ctx, n, it->second.box, it->second.pbc, (char *)sys, L);
+    if (rc) return rc;
+    const Seg &S = L.seg;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t np = S.npad;
+    std::vector<int> perm(np), lcnt(np), scnt(np);
+    std::vector<uint32_t> lidx(np * S.Wl), sidx(np * S.Ws);
+    std::vector<double> off(3 * np);
+    const size_t v4 = ctx->opts.fp64 ? 32 : 16;
+    std::vector<char> xs(v4 * np);
+    HIPCHK(hipMemcpyAsync(perm.data(), S.perm, 4 * np, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(lcnt.data(), S.lcnt, 4 * np, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(scnt.data(), S.scnt, 4 * np, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(lidx.data(), S.lidx, 4 * np * S.Wl, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(sidx.data(), S.sidx, 4 * np * S.Ws, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(xs.data(), S.xs, v4 * np, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    auto pos = [&](int s, int a) -> double {
+        if (ctx->opts.fp64) return ((const double *)xs.data())[4 * s + a];
+        return (double)((const float *)xs.data())[4 * s + a];
+    };
+    auto emit = [&](int s, const uint32_t *row, int cnt, int cap, int *counts, int *jj, double *dd) {
+        const int i = perm[s];
+        counts[i] = std::min(cnt, cap);
+        for (int e = 0; e < counts[i]; e++) {
+            const int j = (int)(row[e] & J_MASK), c = (int)(row[e] >> CODE_SHIFT);
+            const int d0 = c / 49 - 3, d1 = (c / 7) % 7 - 3, d2 = c % 7 - 3;
+            jj[(size_t)i * cap + e] = perm[j];
+            for (int a = 0; a < 3; a++)
+                dd[3 * ((size_t)i * cap + e) + a] =
+                    pos(j, a) - pos(s, a) + (d0 * S.cw[0][a] + d1 * S.cw[1][a] + d2 * S.cw[2][a]);
+        }
+    };
+    for (int s = 0; s < n; s++) {
+        if (cl) emit(s, &lidx[(size_t)s * S.Wl], lcnt[s], long_cap, cl, jl, dl);
+        if (cs) emit(s, &sidx[(size_t)s * S.Ws], scnt[s], short_cap, cs, js, ds);
+    }
+    return CTBOP_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,213 @@
+// ctbop_dev.h -- device-side data structures shared by the HIP kernels.
+//
+// Work decomposition: every kernel runs on a table of tiles.  A tile is 256
+// consecutive rows (atoms, in the sorted frame) of one segment (one atomic
+// system), processed by one 256-thread block.  Segments are padded to whole
+// tiles, so each block touches one segment only; per-tile partial sums are
+// combined per segment in a fixed order by the segment's last block, which
+// makes every reduction deterministic and independent of what else runs in
+// the same launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ctbop {
+
+constexpr int TILE = 256;
+constexpr int NPART = 8;               // doubles of partial sums per tile
+constexpr int CODE_BITS = 9;           // stencil offset code in the list entry
+constexpr int CODE_SHIFT = 23;         // low 23 bits: neighbour row
+constexpr uint32_t J_MASK = (1u << CODE_SHIFT) - 1u;
+constexpr int NCODE = 343;             // offsets (-3..3)^3
+constexpr int CODE_CENTER = 171;       // offset (0,0,0)
+constexpr int MAX_ATOMS = (1 << CODE_SHIFT) - 1;
+
+// status bits (mapped to CTBOP_E_* codes on the host)
+constexpr int ST_TOO_CLOSE = 1, ST_NOCONV = 2, ST_NOT_PD = 4, ST_OVERFLOW = 8, ST_REV = 16;
+
+// ---------------------------------------------------------------------------
+// potential parameters, precomputed on the host per context
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Params {
+    // pair (ti*2 + tj): repulsion/attraction, cutoff radii, pi/(S-R)
+    R A[4], B[4], lam1[4], lam2[4], Rc[4], Sc[4], piSR[4];
+    // centre species: normalisation G, 1/(2 sigma), channel constants
+    R G[2], inv2sig[2];
+    R gam[2][2], c2[2][2], d2[2][2], h[2][2], nn[2][2], g[2][2], alpha[2][2];
+    R p;
+    int p_is_2;
+    int alpha_zero[2];                 // both channels of species t have alpha == 0
+    // Coulomb
+    R ke, rc, inv_rc, g3[4];           // g3 = (gamma_i gamma_j)^(-3/2)
+    double chi[2], J[2], E0[2], mass[2];
+    // list radii (squared), including the skin
+    float l_cut2, s_cut2[4];
+    float close2;                      // too-close threshold squared
+};
+
+// ---------------------------------------------------------------------------
+// per-segment scalars (device), reset per call where noted
+// ---------------------------------------------------------------------------
+struct SegState {
+    int rebuild;       // lists rebuilt in this call
+    int ticket;        // last-block detection counter (returns to 0)
+    int done;          // charge solve finished
+    int iters;
+    int status;        // ST_* bits, sticky until the next rebuild/call reset
+    int maxl, maxs;    // largest list rows at the last build
+    int built;         // lists exist
+    double w;          // current residual shift
+    double rho, alpha, beta, res;
+    double sdinv;      // sum of 1/diag
+    double mu_prev;    // chemical potential of the previous solve
+    double mshift;     // accumulated shift: r_stored = -(Hq+chi) + mshift
+    double qshift;     // final re-projection of q onto sum q = Q
+    double energy;
+    unsigned long long nnz_long, nnz_short;   // list entries at the last build
+    double pad[2];
+};
+
+// ---------------------------------------------------------------------------
+// segment descriptor: geometry, sizes and array addresses
+// ---------------------------------------------------------------------------
+struct Seg {
+    double h[3][3];    // cell vectors as rows
+    double hi[3][3];   // inverse: frac = x . hi
+    double cw[3][3];   // cell-grid vectors: h[d] / nb[d]
+    int pbc[3];
+    int nb[3];         // cell grid
+    int st[3];         // stencil half-width per direction (<= 3)
+    int ncell;
+    int n, npad;       // atoms, padded to TILE
+    int tile0, ntile;  // this segment's range in the tile table
+    int Wl, Ws;        // list capacities (row strides)
+    double Q;          // total charge
+    double skin;
+    // caller arrays (set per call)
+    const double *x;   // SoA positions, 3n
+    const int *type;   // n
+    double *F;         // SoA forces out, 3n
+    double *q_out;     // n
+    double *E_out;     // 1
+    // persistent arrays
+    int *perm;         // sorted row -> user index        [npad]
+    int *cell_of;      // user index -> cell              [n]
+    int *csort;        // sorted row -> cell              [npad]
+    int *cell_start;   // [ncell + 1]
+    int *cell_cnt;     // [ncell]
+    double *off;       // sorted: wrap*h - cell origin, SoA [3 npad]
+    double *ref_x;     // user order positions at build, SoA [3n]
+    void *xs;          // sorted local coordinates + type  [npad] float4 / double4
+    double4 *xs64;     // the same in FP64 (bond lengths of the energy)  [npad]
+    int *lcnt;         // [npad]
+    uint32_t *lidx;    // [npad * Wl]
+    void *H;           // [npad * Wl] float / double
+    int *scnt;         // [npad]
+    uint32_t *sidx;    // [npad * Ws]
+    uint8_t *srev;     // [npad * Ws]
+    void *slot;        // [npad * Ws] float4 / double4: b, P1, P2, -
+    double *ecov;      // [npad]
+    double *Fcov;      // SoA [3 npad]
+    double *q, *r, *p, *s, *dinv, *jd;   // [npad]
+    double *q_state;   // user order charges kept for the warm start [n]
+    double *part;      // [ntile * NPART]
+    SegState *sst;
+};
+
+struct Tile {
+    int seg, row0;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
+__device__ __forceinline__ int code_of(int d0, int d1, int d2) { return ((d0 + 3) * 7 + (d1 + 3)) * 7 + (d2 + 3); }
+
+// reverse offset code: (-d0, -d1, -d2)
+__device__ __forceinline__ int code_neg(int c) { return (NCODE - 1) - c; }
+
+// wave64 sum of a double (fixed butterfly order: deterministic)
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// sum across a group of `width` consecutive lanes (power of two <= 64)
+template <int W>
+__device__ __forceinline__ double group_sum(double v)
+{
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+    return v;
+}
+
+template <int W>
+__device__ __forceinline__ float group_sumf(float v)
+{
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+    return v;
+}
+
+// Block (256 threads) sum of K doubles per thread into out[0..K) (valid in
+// thread 0).  Wave butterflies, then the 4 wave results in a fixed order.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double *lds /* 4*K */, double (&out)[K])
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        double s = wave_sum(v[k]);
+        if (lane == 0) lds[wv * K + k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; k++) out[k] = ((lds[k] + lds[K + k]) + lds[2 * K + k]) + lds[3 * K + k];
+    }
+    __syncthreads();
+}
+
+// Write this tile's K partial sums, and return true in the block that
+// completes the segment (its last tile to finish).  In that block every thread
+// may then read all partials of the segment.
+template <int K>
+__device__ __forceinline__ bool tile_commit(const Seg &S, int tile_local, const double (&part)[K], int *is_last_lds)
+{
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; k++) S.part[tile_local * NPART + k] = part[k];
+        __threadfence();
+        int t = atomicAdd(&S.sst->ticket, 1);
+        *is_last_lds = (t == S.ntile - 1);
+    }
+    __syncthreads();
+    bool last = *is_last_lds;
+    if (last) __threadfence();
+    return last;
+}
+
+// Sum partial k over the segment's tiles in a fixed order (called by all 256
+// threads of the last block; result valid in thread 0).
+template <int K>
+__device__ __forceinline__ void segment_total(const Seg &S, double *lds, double (&out)[K])
+{
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) v[k] = 0.0;
+    for (int t = threadIdx.x; t < S.ntile; t += TILE) {
+        const volatile double *pp = S.part + (size_t)t * NPART;
+#pragma unroll
+        for (int k = 0; k < K; k++) v[k] += pp[k];
+    }
+    block_sum<K>(v, lds, out);
+}
+
+} // namespace ctbop

@@ -1,0 +1,353 @@
+// k_lists.hip -- cell binning, deterministic counting sort into cell order,
+// and the two Verlet neighbour lists built from a cell stencil.
+//
+// Atoms are binned on a grid of at least (rc + skin)/2 wide cells laid along
+// the (possibly tilted) cell vectors.  Rows of every later kernel are atoms in
+// cell order ("sorted rows").  Each sorted atom keeps FP32 coordinates local
+// to its cell's origin; the vector to a neighbour in a cell offset by
+// d = (d0, d1, d2) grid steps (periodic images included) is
+//     r = (l_j - l_i) + D(d),   D(d) = d0 h0/nb0 + d1 h1/nb1 + d2 h2/nb2,
+// which keeps every pair vector exact to FP32 rounding of a few Angstrom,
+// independent of the box size.  A list entry packs the neighbour row (23 bits)
+// and the code of d (9 bits, |d_k| <= 3).
+#pragma once
+#include "ctbop_dev.h"
+
+namespace ctbop {
+
+__global__ void k_set_seg(Seg *dst, Seg src) { *dst = src; }
+
+__global__ void k_call_init(Seg *segs, int nseg, int force_rebuild)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nseg) return;
+    SegState *st = segs[k].sst;
+    st->rebuild = (force_rebuild || !st->built) ? 1 : 0;
+    st->ticket = 0;
+    st->done = 0;
+    st->iters = 0;
+    st->status = 0;
+}
+
+// A neighbour list rebuild is needed once any atom moved more than skin/2
+// since the last build (then no pair can have crossed into the cutoff).
+__global__ void k_check_disp(const Tile *tiles, Seg *segs)
+{
+    const Tile T = tiles[blockIdx.x];
+    const Seg &S = segs[T.seg];
+    if (S.sst->rebuild) return;
+    const int i = T.row0 + threadIdx.x;
+    if (i >= S.n) return;
+    double dx = S.x[i] - S.ref_x[i];
+    double dy = S.x[S.n + i] - S.ref_x[S.n + i];
+    double dz = S.x[2 * S.n + i] - S.ref_x[2 * S.n + i];
+    double lim = 0.5 * S.skin;
+    if (dx * dx + dy * dy + dz * dz > lim * lim) S.sst->rebuild = 1;
+}
+
+// fractional coordinates, folded along periodic vectors; the integer fold is
+// returned in w
+__device__ __forceinline__ void frac_wrap(const Seg &S, double x, double y, double z, double s[3], double w[3])
+{
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+        s[b] = x * S.hi[0][b] + y * S.hi[1][b] + z * S.hi[2][b];
+        w[b] = S.pbc[b] ? -floor(s[b]) : 0.0;
+        s[b] += w[b];
+    }
+}
+
+__device__ __forceinline__ int cell_index(const Seg &S, const double s[3], int c[3])
+{
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+        int v = (int)floor(s[b] * S.nb[b]);
+        c[b] = v < 0 ? 0 : (v >= S.nb[b] ? S.nb[b] - 1 : v);
+    }
+    return (c[0] * S.nb[1] + c[1]) * S.nb[2] + c[2];
+}
+
+// clear cell counters; mark padding rows
+__global__ void k_bin_clear(const Tile *tiles, Seg *segs)
+{
+    const Tile T = tiles[blockIdx.x];
+    const Seg &S = segs[T.seg];
+    if (!S.sst->rebuild) return;
+    const int tl = T.row0 / TILE;
+    for (int c = tl * TILE + threadIdx.x; c < S.ncell; c += S.ntile * TILE) S.cell_cnt[c] = 0;
+    int row = T.row0 + threadIdx.x;
+    if (row >= S.n && row < S.npad) {
+        S.perm[row] = -1;
+        S.csort[row] = 0;
+        S.lcnt[row] = 0;
+        S.scnt[row] = 0;
+    }
+    if (tl == 0 && threadIdx.x == 0) {
+        S.sst->maxl = 0;
+        S.sst->maxs = 0;
+        S.sst->nnz_long = 0;
+        S.sst->nnz_short = 0;
+    }
+}
+
+__global__ void k_bin(const Tile *tiles, Seg *segs)
+{
+    const Tile T = tiles[blockIdx.x];
+    const Seg &S = segs[T.seg];
+    if (!S.sst->rebuild) return;
+    const int i = T.row0 + threadIdx.x;
+    if (i >= S.n) return;
+    double s[3], w[3];
+    int c[3];
+    frac_wrap(S, S.x[i], S.x[S.n + i], S.x[2 * S.n + i], s, w);
+    int ci = cell_index(S, s, c);
+    S.cell_of[i] = ci;
+    atomicAdd(&S.cell_cnt[ci], 1);
+}
+
+// exclusive scan of the cell counts (one block per segment); the counts are
+// zeroed for use as fill counters
+__global__ void k_scan(const int *seg_ids, Seg *segs)
+{
+    const Seg &S = segs[seg_ids[blockIdx.x]];
+    if (!S.sst->rebuild) return;
+    __shared__ int lds[TILE];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < S.ncell; base += TILE) {
+        int c = base + threadIdx.x;
+        int v = c < S.ncell ? S.cell_cnt[c] : 0;
+        lds[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < TILE; o <<= 1) {          // Hillis-Steele inclusive scan
+            int a = threadIdx.x >= o ? lds[threadIdx.x - o] : 0;
+            __syncthreads();
+            lds[threadIdx.x] += a;
+            __syncthreads();
+        }
+        if (c < S.ncell) {
+            S.cell_start[c] = carry + lds[threadIdx.x] - v;
+            S.cell_cnt[c] = 0;
+        }
+        __syncthreads();
+        if (threadIdx.x == TILE - 1) carry += lds[TILE - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) S.cell_start[S.ncell] = carry;
+}
+
+__global__ void k_scatter(const Tile *tiles, Seg *segs)
+{
+    const Tile T = tiles[blockIdx.x];
+    const Seg &S = segs[T.seg];
+    if (!S.sst->rebuild) return;
+    const int i = T.row0 + threadIdx.x;
+    if (i >= S.n) return;
+    int c = S.cell_of[i];
+    int slot = S.cell_start[c] + atomicAdd(&S.cell_cnt[c], 1);
+    S.perm[slot] = i;
+}
+
+// Order each cell's atoms by user index (the scatter's order is arbitrary),
+// so the sorted frame -- and every sum over it -- is deterministic.  Then
+// record, per sorted row, its cell, its offset (fold minus cell origin) and
+// the reference positions for the displacement test.
+__global__ void k_cell_sort(const Tile *tiles, Seg *segs)
+{
+    const Tile T = tiles[blockIdx.x];
+    const Seg &S = segs[T.seg];
+    if (!S.sst->rebuild) return;
+    const int tl = T.row0 / TILE;
+    for (int c = tl * TILE + threadIdx.x; c < S.ncell; c += S.ntile * TILE) {
+        const int a = S.cell_start[c], b = S.cell_start[c + 1];
+        for (int k = a + 1; k < b; k++) {              // insertion sort, cells hold few atoms
+            int v = S.perm[k], m = k - 1;
+            while (m >= a && S.perm[m] > v) { S.perm[m + 1] = S.perm[m]; m--; }
+            S.perm[m + 1] = v;
+        }
+        const int c0 = c / (S.nb[1] * S.nb[2]), c1 = (c / S.nb[2]) % S.nb[1], c2 = c % S.nb[2];
+        for (int k = a; k < b; k++) {
+            const int i = S.perm[k];
+            const double x = S.x[i], y = S.x[S.n + i], z = S.x[2 * S.n + i];
+            double s[3], w[3];
+            frac_wrap(S, x, y, z, s, w);
+            S.csort[k] = c;
+#pragma unroll
+            for (int a2 = 0; a2 < 3; a2++) {
+                double o = w[0] * S.h[0][a2] + w[1] * S.h[1][a2] + w[2] * S.h[2][a2]
+                         - (c0 * S.cw[0][a2] + c1 * S.cw[1][a2] + c2 * S.cw[2][a2]);
+                S.off[a2 * S.npad + k] = o;
+            }
+            S.ref_x[i] = x;
+            S.ref_x[S.n + i] = y;
+            S.ref_x[2 * S.n + i] = z;
+        }
+    }
+}
+
+// local coordinates of every sorted atom for this call's positions, and the
+// warm-start charges in the sorted frame (with their sum, for the projection)
+template <typename R>
+__global__ void k_gather(const Tile *tiles, Seg *segs, int warm)
+{
+    using V4 = typename Vec4<R>::type;
+    const Tile T = tiles[blockIdx.x];
+    const Seg &S = segs[T.seg];
+    const int s = T.row0 + threadIdx.x;
+    double q0 = 0.0;
+    if (s < S.n) {
+        const int i = S.perm[s];
+        double4 w;
+        w.x = S.x[i] + S.off[s];
+        w.y = S.x[S.n + i] + S.off[S.npad + s];
+        w.z = S.x[2 * S.n + i] + S.off[2 * S.npad + s];
+        w.w = (double)S.type[i];
+        V4 v;
+        v.x = (R)w.x;
+        v.y = (R)w.y;
+        v.z = (R)w.z;
+        v.w = (R)w.w;
+        reinterpret_cast<V4 *>(S.xs)[s] = v;
+        if ((void *)S.xs64 != S.xs) S.xs64[s] = w;
+        q0 = warm ? S.q_state[i] : 0.0;
+        S.q[s] = q0;
+    } else if (s < S.npad) {
+        S.q[s] = 0.0;
+    }
+    __shared__ double lds[4];
+    __shared__ int last;
+    double v1[1] = {q0}, o1[1];
+    block_sum<1>(v1, lds, o1);
+    if (tile_commit<1>(S, T.row0 / TILE, o1, &last)) {
+        double tot[1];
+        segment_total<1>(S, lds, tot);
+        if (threadIdx.x == 0) {
+            S.sst->qshift = (S.Q - tot[0]) / S.n;
+            S.sst->ticket = 0;
+        }
+    }
+}
+
+// apply the projection of the starting charges onto sum q = Q
+__global__ void k_qfix(const Tile *tiles, Seg *segs)
+{
+    const Tile T = tiles[blockIdx.x];
+    const Seg &S = segs[T.seg];
+    const int s = T.row0 + threadIdx.x;
+    if (s < S.n) S.q[s] += S.sst->qshift;
+}
+
+// table of D(code) for the block's segment, in LDS
+template <typename R>
+__device__ __forceinline__ void load_dtab(const Seg &S, typename Vec4<R>::type *tab)
+{
+    for (int c = threadIdx.x; c < NCODE; c += blockDim.x) {
+        int d0 = c / 49 - 3, d1 = (c / 7) % 7 - 3, d2 = c % 7 - 3;
+        typename Vec4<R>::type v;
+        v.x = (R)(d0 * S.cw[0][0] + d1 * S.cw[1][0] + d2 * S.cw[2][0]);
+        v.y = (R)(d0 * S.cw[0][1] + d1 * S.cw[1][1] + d2 * S.cw[2][1]);
+        v.z = (R)(d0 * S.cw[0][2] + d1 * S.cw[1][2] + d2 * S.cw[2][2]);
+        v.w = 0;
+        tab[c] = v;
+    }
+    __syncthreads();
+}
+
+// Both lists for every sorted atom: the cell stencil visited in a fixed order,
+// each cell's atoms in sorted order, so rows are deterministic.
+template <typename R>
+__global__ void k_build(const Tile *tiles, Seg *segs, Params<R> P)
+{
+    using V4 = typename Vec4<R>::type;
+    const Tile T = tiles[blockIdx.x];
+    const Seg &S = segs[T.seg];
+    if (!S.sst->rebuild) return;
+    __shared__ V4 dtab[NCODE];
+    load_dtab<R>(S, dtab);
+    const int s = T.row0 + threadIdx.x;
+    if (s >= S.n) return;
+    const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
+    const V4 li = xs[s];
+    const int ti = (int)li.w;
+    const int c = S.csort[s];
+    const int c0 = c / (S.nb[1] * S.nb[2]), c1 = (c / S.nb[2]) % S.nb[1], c2 = c % S.nb[2];
+    uint32_t *lrow = S.lidx + (size_t)s * S.Wl;
+    uint32_t *srow = S.sidx + (size_t)s * S.Ws;
+    int nl = 0, ns = 0, status = 0;
+    for (int d0 = -S.st[0]; d0 <= S.st[0]; d0++) {
+        int e0 = c0 + d0;
+        if (S.pbc[0]) { e0 %= S.nb[0]; if (e0 < 0) e0 += S.nb[0]; }
+        else if (e0 < 0 || e0 >= S.nb[0]) continue;
+        for (int d1 = -S.st[1]; d1 <= S.st[1]; d1++) {
+            int e1 = c1 + d1;
+            if (S.pbc[1]) { e1 %= S.nb[1]; if (e1 < 0) e1 += S.nb[1]; }
+            else if (e1 < 0 || e1 >= S.nb[1]) continue;
+            for (int d2 = -S.st[2]; d2 <= S.st[2]; d2++) {
+                int e2 = c2 + d2;
+                if (S.pbc[2]) { e2 %= S.nb[2]; if (e2 < 0) e2 += S.nb[2]; }
+                else if (e2 < 0 || e2 >= S.nb[2]) continue;
+                const int code = code_of(d0, d1, d2);
+                const V4 D = dtab[code];
+                const int cc = (e0 * S.nb[1] + e1) * S.nb[2] + e2;
+                const int m0 = S.cell_start[cc], m1 = S.cell_start[cc + 1];
+                for (int m = m0; m < m1; m++) {
+                    if (m == s && code == CODE_CENTER) continue;
+                    const V4 lj = xs[m];
+                    R rx = (lj.x - li.x) + D.x, ry = (lj.y - li.y) + D.y, rz = (lj.z - li.z) + D.z;
+                    float r2 = (float)(rx * rx + ry * ry + rz * rz);
+                    if (r2 >= P.l_cut2) continue;
+                    if (r2 < P.close2) status |= ST_TOO_CLOSE;
+                    const uint32_t ent = (uint32_t)m | ((uint32_t)code << CODE_SHIFT);
+                    if (nl < S.Wl) lrow[nl] = ent;
+                    nl++;
+                    const int tj = (int)lj.w;
+                    if (r2 < P.s_cut2[ti * 2 + tj]) {
+                        if (ns < S.Ws) srow[ns] = ent;
+                        ns++;
+                    }
+                }
+            }
+        }
+    }
+    if (nl > S.Wl || ns > S.Ws) status |= ST_OVERFLOW;
+    S.lcnt[s] = nl < S.Wl ? nl : S.Wl;
+    S.scnt[s] = ns < S.Ws ? ns : S.Ws;
+    atomicMax(&S.sst->maxl, nl);
+    atomicMax(&S.sst->maxs, ns);
+    atomicAdd(&S.sst->nnz_long, (unsigned long long)S.lcnt[s]);
+    atomicAdd(&S.sst->nnz_short, (unsigned long long)S.scnt[s]);
+    if (status) atomicOr(&S.sst->status, status);
+}
+
+// For every covalent entry (i -> j, d) the slot of (j -> i, -d) in row j.
+__global__ void k_rev(const Tile *tiles, Seg *segs)
+{
+    const Tile T = tiles[blockIdx.x];
+    const Seg &S = segs[T.seg];
+    if (!S.sst->rebuild) return;
+    const int s = T.row0 + threadIdx.x;
+    if (s >= S.n) return;
+    const int ns = S.scnt[s];
+    int bad = 0;
+    for (int e = 0; e < ns; e++) {
+        const uint32_t ent = S.sidx[(size_t)s * S.Ws + e];
+        const int j = (int)(ent & J_MASK), want = code_neg((int)(ent >> CODE_SHIFT));
+        const uint32_t target = (uint32_t)s | ((uint32_t)want << CODE_SHIFT);
+        const int nj = S.scnt[j];
+        int f = -1;
+        for (int k = 0; k < nj; k++)
+            if (S.sidx[(size_t)j * S.Ws + k] == target) { f = k; break; }
+        if (f < 0) { bad = 1; f = 0; }
+        S.srev[(size_t)s * S.Ws + e] = (uint8_t)f;
+    }
+    if (bad) atomicOr(&S.sst->status, ST_REV);
+}
+
+__global__ void k_mark_built(Seg *segs, int nseg)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nseg && segs[k].sst->rebuild) segs[k].sst->built = 1;
+}
+
+} // namespace ctbop

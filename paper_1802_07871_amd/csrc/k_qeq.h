@@ -1,0 +1,319 @@
+// k_qeq.h -- charge equilibration and the Coulomb terms.
+//
+// The charges minimise the energy at every call (Methods).  With the
+// self energy chi q + J q^2/2 and the Coulomb kernel C_ij, the energy is
+// quadratic in q, so the minimiser solves  H q + chi = mu 1,  sum q = Q,
+// H = diag(J) + [C_ij summed over images].  It is found by projected
+// Jacobi-preconditioned conjugate gradients:
+//   z = D^-1 (r - w 1),  w = (1^T D^-1 r) / (1^T D^-1 1),
+// which keeps every direction on sum z = 0.  The residual r is stored shifted
+// by the running w (r = -(Hq + chi) + const), so it never carries the large
+// multiplier mu, whose rounding would otherwise swamp r^T z.  Vectors,
+// dot products and the projection are FP64; the matrix entries are stored in
+// the pair precision (FP32 in the mixed build).
+//
+// Rows of the Coulomb list are processed by LPR consecutive lanes each; rows
+// are stored row-major (stride Wl), so the lanes of a row read contiguous
+// memory and their partial sums combine by a fixed butterfly.
+#pragma once
+#include "ctbop_dev.h"
+#include "k_tersoff.h"
+
+namespace ctbop {
+
+// Shielded, tapered Coulomb kernel C(r) = ke T(r/rc) (r^3 + g3)^(-1/3) and
+// dC/dr, evaluated in FP64 for a given distance: the FP32 reciprocal cube
+// root seeds one Newton step, y <- y (4 - u y^3) / 3, which leaves a relative
+// error of ~1e-14, so the only error left in the mixed build is the
+// (unbiased) rounding of r itself.  Summed over ~10^5 charged pairs, a
+// one-sided error of the FP32 functions would otherwise bias the energy.
+__device__ __forceinline__ double coul64(const Params<double> &P, int pp, double r, double &dC)
+{
+    const double x = r * P.inv_rc, x2 = x * x, x3 = x2 * x;
+    const double om = 1.0 - x, om2 = om * om;
+    const double T = om2 * om2 * (1.0 + 4.0 * x + 10.0 * x2 + 20.0 * x3);
+    const double dT = -140.0 * x3 * om2 * om;
+    const double u = r * r * r + P.g3[pp];
+    double y = (double)rcbrtf((float)u);
+    y = y * (4.0 - u * y * y * y) * (1.0 / 3.0);
+    const double y2 = y * y;
+    dC = P.ke * (dT * P.inv_rc * y - T * r * r * y2 * y2);
+    return P.ke * T * y;
+}
+
+__device__ __forceinline__ double coul64_val(const Params<double> &P, int pp, double r)
+{
+    const double x = r * P.inv_rc, x2 = x * x, x3 = x2 * x;
+    const double om = 1.0 - x, om2 = om * om;
+    const double T = om2 * om2 * (1.0 + 4.0 * x + 10.0 * x2 + 20.0 * x3);
+    const double u = r * r * r + P.g3[pp];
+    double y = (double)rcbrtf((float)u);
+    y = y * (4.0 - u * y * y * y) * (1.0 / 3.0);
+    return P.ke * T * y;
+}
+
+struct CgCtl {
+    double tol;
+    int maxit;
+};
+
+// Assemble the Coulomb entries of every row, the diagonal (J plus self
+// images) and the starting residual r = -(H q0 + chi) + mu_prev.
+template <typename R, int LPR>
+__global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs, Params<R> P, Params<double> PD,
+                                                   CgCtl ctl)
+{
+    using V4 = typename Vec4<R>::type;
+    const Tile T = tiles[blockIdx.x];
+    const Seg &S = segs[T.seg];
+    __shared__ V4 dtab[NCODE];
+    __shared__ double lds[4 * 5];
+    __shared__ int last;
+    load_dtab2<R>(S, dtab);
+    const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
+    R *H = reinterpret_cast<R *>(S.H);
+    const double mprev = S.sst->mu_prev;
+    constexpr int G = TILE / LPR;
+    const int lane = threadIdx.x % LPR;
+    double acc5[5] = {0, 0, 0, 0, 0};
+    for (int k = threadIdx.x / LPR; k < TILE; k += G) {
+        const int s = T.row0 + k;
+        if (s >= S.n) continue;
+        const V4 li = xs[s];
+        const int ti = (int)li.w;
+        const int cnt = S.lcnt[s];
+        const uint32_t *row = S.lidx + (size_t)s * S.Wl;
+        R *hrow = H + (size_t)s * S.Wl;
+        double acc = 0.0, self = 0.0;
+        for (int e = lane; e < cnt; e += LPR) {
+            const uint32_t ent = row[e];
+            const int j = (int)(ent & J_MASK);
+            const V4 lj = xs[j];
+            const R3<R> d = pair_vec<R>(li, lj, dtab[ent >> CODE_SHIFT]);
+            const double r = (double)dev_sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
+            const R c = r < PD.rc ? (R)coul64_val(PD, ti * 2 + (int)lj.w, r) : (R)0;
+            hrow[e] = c;
+            acc += (double)c * S.q[j];
+            if (j == s) self += (double)c;
+        }
+        acc = group_sum<LPR>(acc);
+        self = group_sum<LPR>(self);
+        if (lane == 0) {
+            const double qs = S.q[s];
+            const double dg = P.J[ti] + self;
+            const double di = 1.0 / dg;
+            const double r = -(P.J[ti] * qs + acc + P.chi[ti]) + mprev;
+            S.dinv[s] = di;
+            S.jd[s] = P.J[ti];
+            S.r[s] = r;
+            S.p[s] = 0.0;
+            acc5[0] += r * di;
+            acc5[1] += r * r * di;
+            acc5[2] += r;
+            acc5[3] += r * r;
+            acc5[4] += di;
+        }
+    }
+    double tot[5];
+    block_sum<5>(acc5, lds, tot);
+    if (tile_commit<5>(S, T.row0 / TILE, tot, &last)) {
+        segment_total<5>(S, lds, tot);
+        if (threadIdx.x == 0) {
+            SegState *st = S.sst;
+            const double w = tot[0] / tot[4];
+            const double res2 = (tot[3] - tot[2] * tot[2] / S.n) / S.n;
+            st->sdinv = tot[4];
+            st->w = w;
+            st->rho = tot[1] - w * tot[0];
+            st->beta = 0.0;
+            st->res = sqrt(fmax(res2, 0.0));
+            st->mshift = mprev - w;
+            st->iters = 0;
+            st->qshift = 0.0;
+            st->done = (st->res < ctl.tol) ? 1 : 0;
+            st->ticket = 0;
+        }
+    }
+}
+
+// r <- r - w,  p <- D^-1 r + beta p
+__global__ void __launch_bounds__(TILE) k_cg_dir(const Tile *tiles, Seg *segs)
+{
+    const Tile T = tiles[blockIdx.x];
+    const Seg &S = segs[T.seg];
+    if (S.sst->done) return;
+    const int s = T.row0 + threadIdx.x;
+    if (s >= S.n) return;
+    const double w = S.sst->w, beta = S.sst->beta;
+    const double r = S.r[s] - w;
+    S.r[s] = r;
+    S.p[s] = S.dinv[s] * r + beta * S.p[s];
+}
+
+// s = H p and p^T s; the segment's last block sets alpha = rho / p^T H p
+template <typename R, int LPR>
+__global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs, Params<R> P)
+{
+    const Tile T = tiles[blockIdx.x];
+    const Seg &S = segs[T.seg];
+    if (S.sst->done) return;
+    __shared__ double lds[4];
+    __shared__ int last;
+    const R *H = reinterpret_cast<const R *>(S.H);
+    constexpr int G = TILE / LPR;
+    const int lane = threadIdx.x % LPR;
+    double pap = 0.0;
+    for (int k = threadIdx.x / LPR; k < TILE; k += G) {
+        const int s = T.row0 + k;
+        if (s >= S.n) continue;
+        const int cnt = S.lcnt[s];
+        const uint32_t *row = S.lidx + (size_t)s * S.Wl;
+        const R *hrow = H + (size_t)s * S.Wl;
+        double acc = 0.0;
+        for (int e = lane; e < cnt; e += LPR) acc += (double)hrow[e] * S.p[row[e] & J_MASK];
+        acc = group_sum<LPR>(acc);
+        if (lane == 0) {
+            const double ps = S.p[s];
+            const double y = S.jd[s] * ps + acc;
+            S.s[s] = y;
+            pap += ps * y;
+        }
+    }
+    double v[1] = {pap}, tot[1];
+    block_sum<1>(v, lds, tot);
+    if (tile_commit<1>(S, T.row0 / TILE, tot, &last)) {
+        segment_total<1>(S, lds, tot);
+        if (threadIdx.x == 0) {
+            SegState *st = S.sst;
+            if (!(tot[0] > 0.0)) {
+                st->status |= ST_NOT_PD;
+                st->done = 1;
+                st->alpha = 0.0;
+            } else {
+                st->alpha = st->rho / tot[0];
+            }
+            st->ticket = 0;
+        }
+    }
+}
+
+// q += alpha p, r -= alpha s; the last block forms w, rho, beta and tests
+// the projected residual
+__global__ void __launch_bounds__(TILE) k_cg_update(const Tile *tiles, Seg *segs, CgCtl ctl)
+{
+    const Tile T = tiles[blockIdx.x];
+    const Seg &S = segs[T.seg];
+    if (S.sst->done) return;
+    __shared__ double lds[4 * 6];
+    __shared__ int last;
+    const int s = T.row0 + threadIdx.x;
+    const double alpha = S.sst->alpha;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (s < S.n) {
+        const double q = S.q[s] + alpha * S.p[s];
+        const double r = S.r[s] - alpha * S.s[s];
+        const double di = S.dinv[s];
+        S.q[s] = q;
+        S.r[s] = r;
+        v[0] = r * di;
+        v[1] = r * r * di;
+        v[2] = r;
+        v[3] = r * r;
+        v[4] = q;
+    }
+    double tot[6];
+    block_sum<6>(v, lds, tot);
+    if (tile_commit<6>(S, T.row0 / TILE, tot, &last)) {
+        segment_total<6>(S, lds, tot);
+        if (threadIdx.x == 0) {
+            SegState *st = S.sst;
+            const double w = tot[0] / st->sdinv;
+            const double rho = tot[1] - w * tot[0];
+            const double res2 = (tot[3] - tot[2] * tot[2] / S.n) / S.n;
+            st->beta = rho / st->rho;
+            st->rho = rho;
+            st->w = w;
+            st->mshift -= w;
+            st->res = sqrt(fmax(res2, 0.0));
+            st->iters += 1;
+            st->qshift = (S.Q - tot[4]) / S.n;
+            if (st->res < ctl.tol) st->done = 1;
+            else if (st->iters >= ctl.maxit) { st->done = 1; st->status |= ST_NOCONV; }
+            st->ticket = 0;
+        }
+    }
+}
+
+// Coulomb forces and energy at the equilibrated charges, plus the covalent
+// forces and energies: writes F, q (user order) and the total energy.
+template <typename R, int LPR>
+__global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *segs, Params<R> P, Params<double> PD)
+{
+    using V4 = typename Vec4<R>::type;
+    const Tile T = tiles[blockIdx.x];
+    const Seg &S = segs[T.seg];
+    __shared__ V4 dtab[NCODE];
+    __shared__ double lds[4];
+    __shared__ int last;
+    load_dtab2<R>(S, dtab);
+    const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
+    const double qsh = S.sst->qshift;
+    constexpr int G = TILE / LPR;
+    const int lane = threadIdx.x % LPR;
+    double esum = 0.0;
+    for (int k = threadIdx.x / LPR; k < TILE; k += G) {
+        const int s = T.row0 + k;
+        if (s >= S.n) continue;
+        const V4 li = xs[s];
+        const int ti = (int)li.w;
+        const int cnt = S.lcnt[s];
+        const uint32_t *row = S.lidx + (size_t)s * S.Wl;
+        double ec = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+        for (int e = lane; e < cnt; e += LPR) {
+            const uint32_t ent = row[e];
+            const int j = (int)(ent & J_MASK);
+            const V4 lj = xs[j];
+            const R3<R> d = pair_vec<R>(li, lj, dtab[ent >> CODE_SHIFT]);
+            const double r = (double)dev_sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
+            if (r >= PD.rc) continue;
+            double dC;
+            const double c = coul64(PD, ti * 2 + (int)lj.w, r, dC);
+            const double qj = S.q[j] + qsh;
+            ec += c * qj;
+            if (j != s) {
+                const double g = qj * dC / r;
+                fx += g * (double)d.x;
+                fy += g * (double)d.y;
+                fz += g * (double)d.z;
+            }
+        }
+        ec = group_sum<LPR>(ec);
+        fx = group_sum<LPR>(fx);
+        fy = group_sum<LPR>(fy);
+        fz = group_sum<LPR>(fz);
+        if (lane == 0) {
+            const double qs = S.q[s] + qsh;
+            const int i = S.perm[s];
+            S.F[i] = qs * fx + S.Fcov[s];
+            S.F[S.n + i] = qs * fy + S.Fcov[S.npad + s];
+            S.F[2 * S.n + i] = qs * fz + S.Fcov[2 * S.npad + s];
+            S.q_out[i] = qs;
+            S.q_state[i] = qs;
+            esum += P.E0[ti] + P.chi[ti] * qs + 0.5 * P.J[ti] * qs * qs + 0.5 * qs * ec + S.ecov[s];
+        }
+    }
+    double v[1] = {esum}, tot[1];
+    block_sum<1>(v, lds, tot);
+    if (tile_commit<1>(S, T.row0 / TILE, tot, &last)) {
+        segment_total<1>(S, lds, tot);
+        if (threadIdx.x == 0) {
+            SegState *st = S.sst;
+            st->energy = tot[0];
+            if (S.E_out) *S.E_out = tot[0];
+            st->mu_prev = st->mshift;
+            st->ticket = 0;
+        }
+    }
+}
+
+} // namespace ctbop

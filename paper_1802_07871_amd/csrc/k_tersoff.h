@@ -1,0 +1,341 @@
+// k_tersoff.h -- covalent part: bond pass and atomic-free force gather.
+//
+// Bond pass (one lane per sorted atom i): for every covalent-list entry
+// (i -> j) inside the cutoff S_ij, the environment sums of the two channels
+//     zeta_l,ij = sum_{k != j} fc(r_ik) w_l(cos theta_ijk) exp[(alpha_l (r_ij - r_ik))^3]
+// (Methods, Eq. 2, one per channel), the vectorised bond order
+//     b_ij = G (sum_l (g_l + zeta_l^n_l)^-p)^(1/(2 sigma p))       (Eqs. 3-5, 7)
+// and the bond energy 1/2 fc (fR - b fA).  Per entry it stores b_ij and the
+// coefficients P_l = dE/dzeta_l,ij = -1/2 fc fA db/dzeta_l.
+//
+// Force gather (one lane per sorted atom m) writes only F_m: every covalent
+// term that moves with x_m, read back from the stored coefficients:
+//   m as the centre i  : its own bonds (pair term) and their k environments;
+//   m as the partner j : bonds (i -> m) of each neighbour i, found through the
+//                        reverse-slot index, with i's environment k;
+//   m as environment k : bonds (i -> k) of each neighbour i, with m in them.
+// No atomics: each F_m is a plain sum in a fixed order (deterministic).
+#pragma once
+#include "ctbop_dev.h"
+
+namespace ctbop {
+
+template <typename R> struct R3 { R x, y, z; };
+
+template <typename R>
+__device__ __forceinline__ R dev_sqrt(R v) { return sqrt(v); }
+
+__device__ __forceinline__ void dev_sincos(float a, float *s, float *c) { sincosf(a, s, c); }
+__device__ __forceinline__ void dev_sincos(double a, double *s, double *c) { sincos(a, s, c); }
+
+template <typename R>
+__device__ __forceinline__ R cutoff(R r, R Rc, R Sc, R piSR, R &dfc)
+{
+    if (r <= Rc) { dfc = (R)0; return (R)1; }
+    if (r >= Sc) { dfc = (R)0; return (R)0; }
+    R sn, cs;
+    dev_sincos(piSR * (r - Rc), &sn, &cs);
+    dfc = (R)-0.5 * piSR * sn;
+    return (R)0.5 + (R)0.5 * cs;
+}
+
+// angular function of channel l for centre species t (and d/dcos)
+template <typename R>
+__device__ __forceinline__ R angular(const Params<R> &P, int t, int l, R cs, R &dw)
+{
+    R x = P.h[t][l] - cs;
+    R den = P.d2[t][l] + x * x;
+    R w = P.gam[t][l] * ((R)1 + P.c2[t][l] * x * x / (P.d2[t][l] * den));
+    dw = -P.gam[t][l] * P.c2[t][l] * (R)2 * x / (den * den);
+    return w;
+}
+
+template <typename R>
+__device__ __forceinline__ R radial(const Params<R> &P, int t, int l, R dl, R &de)
+{
+    R a = P.alpha[t][l] * dl;
+    R e = exp(a * a * a);
+    de = (R)3 * P.alpha[t][l] * a * a * e;
+    return e;
+}
+
+// vectorised bond order and its derivatives in zeta_1, zeta_2
+template <typename R>
+__device__ __forceinline__ R bond_order(const Params<R> &P, int t, R z1, R z2, R &db1, R &db2)
+{
+    R zn1 = z1 > (R)0 ? pow(z1, P.nn[t][0]) : (R)0;
+    R zn2 = z2 > (R)0 ? pow(z2, P.nn[t][1]) : (R)0;
+    R zh1 = P.g[t][0] + zn1, zh2 = P.g[t][1] + zn2;
+    R a1, a2, S, b;
+    if (P.p_is_2) {
+        R i1 = (R)1 / zh1, i2 = (R)1 / zh2;
+        a1 = i1 * i1;
+        a2 = i2 * i2;
+        S = a1 + a2;
+        b = P.G[t] * pow(S, P.inv2sig[t] * (R)0.5);
+        a1 *= i1;                    // zh^-p-1
+        a2 *= i2;
+    } else {
+        a1 = pow(zh1, -P.p);
+        a2 = pow(zh2, -P.p);
+        S = a1 + a2;
+        b = P.G[t] * pow(S, P.inv2sig[t] / P.p);
+        a1 /= zh1;
+        a2 /= zh2;
+    }
+    R k = -b * P.inv2sig[t] / S;
+    db1 = z1 > (R)0 ? k * P.nn[t][0] * (zn1 / z1) * a1 : (R)0;
+    db2 = z2 > (R)0 ? k * P.nn[t][1] * (zn2 / z2) * a2 : (R)0;
+    return b;
+}
+
+// Gradients w.r.t. the bond partner (gj) and the environment atom (gk) of the
+// zeta_l term of a triplet: centre species tc, bond vector db (length rb),
+// environment vector de (length re), environment cutoff pair penv.
+template <typename R>
+__device__ __forceinline__ void trip_grad(const Params<R> &P, int tc, int penv, const R3<R> &db, R rb,
+                                          const R3<R> &de, R re, R3<R> gj[2], R3<R> gk[2])
+{
+    const R ib = (R)1 / rb, ie = (R)1 / re;
+    const R3<R> ub = {db.x * ib, db.y * ib, db.z * ib};
+    const R3<R> ue = {de.x * ie, de.y * ie, de.z * ie};
+    const R cs = ub.x * ue.x + ub.y * ue.y + ub.z * ue.z;
+    const R3<R> cb = {(ue.x - cs * ub.x) * ib, (ue.y - cs * ub.y) * ib, (ue.z - cs * ub.z) * ib};
+    const R3<R> ce = {(ub.x - cs * ue.x) * ie, (ub.y - cs * ue.y) * ie, (ub.z - cs * ue.z) * ie};
+    R dfe;
+    const R fe = cutoff(re, P.Rc[penv], P.Sc[penv], P.piSR[penv], dfe);
+#pragma unroll
+    for (int l = 0; l < 2; l++) {
+        R dw, de_ = (R)0, ex = (R)1;
+        const R w = angular(P, tc, l, cs, dw);
+        if (!P.alpha_zero[tc]) ex = radial(P, tc, l, rb - re, de_);
+        const R a = fe * dw * ex, bcoef = fe * w * de_, c = dfe * w * ex;
+        gj[l].x = a * cb.x + bcoef * ub.x;
+        gj[l].y = a * cb.y + bcoef * ub.y;
+        gj[l].z = a * cb.z + bcoef * ub.z;
+        gk[l].x = c * ue.x + a * ce.x - bcoef * ue.x;
+        gk[l].y = c * ue.y + a * ce.y - bcoef * ue.y;
+        gk[l].z = c * ue.z + a * ce.z - bcoef * ue.z;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ R3<R> pair_vec(const typename Vec4<R>::type &a, const typename Vec4<R>::type &b,
+                                          const typename Vec4<R>::type &D)
+{
+    R3<R> v = {(b.x - a.x) + D.x, (b.y - a.y) + D.y, (b.z - a.z) + D.z};
+    return v;
+}
+
+template <typename R>
+__device__ __forceinline__ void load_dtab2(const Seg &S, typename Vec4<R>::type *tab)
+{
+    for (int c = threadIdx.x; c < NCODE; c += blockDim.x) {
+        int d0 = c / 49 - 3, d1 = (c / 7) % 7 - 3, d2 = c % 7 - 3;
+        typename Vec4<R>::type v;
+        v.x = (R)(d0 * S.cw[0][0] + d1 * S.cw[1][0] + d2 * S.cw[2][0]);
+        v.y = (R)(d0 * S.cw[0][1] + d1 * S.cw[1][1] + d2 * S.cw[2][1]);
+        v.z = (R)(d0 * S.cw[0][2] + d1 * S.cw[1][2] + d2 * S.cw[2][2]);
+        v.w = 0;
+        tab[c] = v;
+    }
+    __syncthreads();
+}
+
+// FP64 vector of a list entry from the FP64 local coordinates
+__device__ __forceinline__ double3 pair_vec64(const Seg &S, const double4 &a, int j, int code)
+{
+    const double4 b = S.xs64[j];
+    const int d0 = code / 49 - 3, d1 = (code / 7) % 7 - 3, d2 = code % 7 - 3;
+    double3 v;
+    v.x = (b.x - a.x) + (d0 * S.cw[0][0] + d1 * S.cw[1][0] + d2 * S.cw[2][0]);
+    v.y = (b.y - a.y) + (d0 * S.cw[0][1] + d1 * S.cw[1][1] + d2 * S.cw[2][1]);
+    v.z = (b.z - a.z) + (d0 * S.cw[0][2] + d1 * S.cw[1][2] + d2 * S.cw[2][2]);
+    return v;
+}
+
+// The environment sums (triplet work) run in the pair precision R; the bond
+// length, fc, fR, fA, b and the bond energy are then evaluated in FP64, so
+// the total energy carries no FP32 rounding of the large, cancelling fR and
+// b fA terms.
+template <typename R>
+__global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Params<R> P, Params<double> PD)
+{
+    using V4 = typename Vec4<R>::type;
+    const Tile T = tiles[blockIdx.x];
+    const Seg &S = segs[T.seg];
+    __shared__ V4 dtab[NCODE];
+    load_dtab2<R>(S, dtab);
+    const int s = T.row0 + threadIdx.x;
+    if (s >= S.n) {
+        if (s < S.npad) S.ecov[s] = 0.0;
+        return;
+    }
+    const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
+    V4 *slot = reinterpret_cast<V4 *>(S.slot) + (size_t)s * S.Ws;
+    const uint32_t *row = S.sidx + (size_t)s * S.Ws;
+    const V4 li = xs[s];
+    const double4 li64 = S.xs64[s];
+    const int ti = (int)li.w;
+    const int ns = S.scnt[s];
+    double ecov = 0.0;
+    for (int e = 0; e < ns; e++) {
+        const uint32_t ent = row[e];
+        const V4 lj = xs[ent & J_MASK];
+        const int tj = (int)lj.w, pp = ti * 2 + tj;
+        const R3<R> d = pair_vec<R>(li, lj, dtab[ent >> CODE_SHIFT]);
+        const R r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+        V4 out;
+        out.x = out.y = out.z = out.w = (R)0;
+        if (r2 < P.Sc[pp] * P.Sc[pp]) {
+            const R r = dev_sqrt(r2);
+            R z1 = 0, z2 = 0;
+            for (int e2 = 0; e2 < ns; e2++) {
+                if (e2 == e) continue;
+                const uint32_t ent2 = row[e2];
+                const V4 lk = xs[ent2 & J_MASK];
+                const int pk = ti * 2 + (int)lk.w;
+                const R3<R> dk = pair_vec<R>(li, lk, dtab[ent2 >> CODE_SHIFT]);
+                const R rk2 = dk.x * dk.x + dk.y * dk.y + dk.z * dk.z;
+                if (rk2 >= P.Sc[pk] * P.Sc[pk]) continue;
+                const R rk = dev_sqrt(rk2);
+                const R cs = (d.x * dk.x + d.y * dk.y + d.z * dk.z) / (r * rk);
+                R dummy;
+                const R fk = cutoff(rk, P.Rc[pk], P.Sc[pk], P.piSR[pk], dummy);
+                R dw, dex;
+                R w1 = angular(P, ti, 0, cs, dw), w2 = angular(P, ti, 1, cs, dw);
+                if (!P.alpha_zero[ti]) {
+                    w1 *= radial(P, ti, 0, r - rk, dex);
+                    w2 *= radial(P, ti, 1, r - rk, dex);
+                }
+                z1 += fk * w1;
+                z2 += fk * w2;
+            }
+            const double3 d64 = pair_vec64(S, li64, (int)(ent & J_MASK), (int)(ent >> CODE_SHIFT));
+            const double rd = sqrt(d64.x * d64.x + d64.y * d64.y + d64.z * d64.z);
+            double db1, db2, dfc;
+            const double b = bond_order<double>(PD, ti, (double)z1, (double)z2, db1, db2);
+            const double fc = cutoff<double>(rd, PD.Rc[pp], PD.Sc[pp], PD.piSR[pp], dfc);
+            const double fR = PD.A[pp] * exp(-PD.lam1[pp] * rd), fA = PD.B[pp] * exp(-PD.lam2[pp] * rd);
+            ecov += 0.5 * fc * (fR - b * fA);
+            out.x = (R)b;
+            out.y = (R)(-0.5 * fc * fA * db1);
+            out.z = (R)(-0.5 * fc * fA * db2);
+        }
+        slot[e] = out;
+    }
+    S.ecov[s] = ecov;
+}
+
+// pair-term derivative dV/dr of 1/2 fc (fR - b fA) at fixed b
+template <typename R>
+__device__ __forceinline__ R pair_dvdr(const Params<R> &P, int pp, R r, R b)
+{
+    R dfc;
+    const R fc = cutoff(r, P.Rc[pp], P.Sc[pp], P.piSR[pp], dfc);
+    const R fR = P.A[pp] * exp(-P.lam1[pp] * r), fA = P.B[pp] * exp(-P.lam2[pp] * r);
+    return (R)0.5 * (dfc * (fR - b * fA) + fc * (-P.lam1[pp] * fR + b * P.lam2[pp] * fA));
+}
+
+template <typename R>
+__global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs, Params<R> P)
+{
+    using V4 = typename Vec4<R>::type;
+    const Tile T = tiles[blockIdx.x];
+    const Seg &S = segs[T.seg];
+    __shared__ V4 dtab[NCODE];
+    load_dtab2<R>(S, dtab);
+    const int m = T.row0 + threadIdx.x;
+    if (m >= S.n) return;
+    const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
+    const V4 *slot = reinterpret_cast<const V4 *>(S.slot);
+    const V4 lm = xs[m];
+    const int tm = (int)lm.w;
+    const int ns = S.scnt[m];
+    const uint32_t *row = S.sidx + (size_t)m * S.Ws;
+    double fx = 0, fy = 0, fz = 0;
+    // m as the centre of its own bonds
+    for (int e = 0; e < ns; e++) {
+        const uint32_t ent = row[e];
+        const V4 lj = xs[ent & J_MASK];
+        const int pp = tm * 2 + (int)lj.w;
+        const R3<R> d = pair_vec<R>(lm, lj, dtab[ent >> CODE_SHIFT]);
+        const R r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+        if (r2 >= P.Sc[pp] * P.Sc[pp]) continue;
+        const R r = dev_sqrt(r2), ir = (R)1 / r;
+        const V4 sv = slot[(size_t)m * S.Ws + e];
+        const R dv = pair_dvdr(P, pp, r, sv.x) * ir;
+        R ax = dv * d.x, ay = dv * d.y, az = dv * d.z;
+        if (sv.y != (R)0 || sv.z != (R)0) {
+            for (int e2 = 0; e2 < ns; e2++) {
+                if (e2 == e) continue;
+                const uint32_t ent2 = row[e2];
+                const V4 lk = xs[ent2 & J_MASK];
+                const int pk = tm * 2 + (int)lk.w;
+                const R3<R> dk = pair_vec<R>(lm, lk, dtab[ent2 >> CODE_SHIFT]);
+                const R rk2 = dk.x * dk.x + dk.y * dk.y + dk.z * dk.z;
+                if (rk2 >= P.Sc[pk] * P.Sc[pk]) continue;
+                R3<R> gj[2], gk[2];
+                trip_grad(P, tm, pk, d, r, dk, dev_sqrt(rk2), gj, gk);
+                ax += sv.y * (gj[0].x + gk[0].x) + sv.z * (gj[1].x + gk[1].x);
+                ay += sv.y * (gj[0].y + gk[0].y) + sv.z * (gj[1].y + gk[1].y);
+                az += sv.z * (gj[1].z + gk[1].z) + sv.y * (gj[0].z + gk[0].z);
+            }
+        }
+        fx += (double)ax;
+        fy += (double)ay;
+        fz += (double)az;
+    }
+    // m as the partner j or the environment k of its neighbours' bonds
+    for (int e = 0; e < ns; e++) {
+        const uint32_t ent = row[e];
+        const int i = (int)(ent & J_MASK);
+        const V4 li = xs[i];
+        const int ti = (int)li.w, pp = ti * 2 + tm;
+        const R3<R> dmi = pair_vec<R>(lm, li, dtab[ent >> CODE_SHIFT]);
+        const R r2 = dmi.x * dmi.x + dmi.y * dmi.y + dmi.z * dmi.z;
+        if (r2 >= P.Sc[pp] * P.Sc[pp]) continue;
+        const R r = dev_sqrt(r2), ir = (R)1 / r;
+        const R3<R> d = {-dmi.x, -dmi.y, -dmi.z};            // i -> m
+        const int srev = S.srev[(size_t)m * S.Ws + e];
+        const V4 sv = slot[(size_t)i * S.Ws + srev];          // bond (i -> m)
+        const R dv = pair_dvdr(P, pp, r, sv.x) * ir;
+        R ax = -dv * d.x, ay = -dv * d.y, az = -dv * d.z;
+        const int ni = S.scnt[i];
+        const uint32_t *rowi = S.sidx + (size_t)i * S.Ws;
+        for (int t = 0; t < ni; t++) {
+            if (t == srev) continue;
+            const uint32_t ent2 = rowi[t];
+            const V4 lk = xs[ent2 & J_MASK];
+            const int pk = ti * 2 + (int)lk.w;
+            const R3<R> dk = pair_vec<R>(li, lk, dtab[ent2 >> CODE_SHIFT]);   // i -> k
+            const R rk2 = dk.x * dk.x + dk.y * dk.y + dk.z * dk.z;
+            if (rk2 >= P.Sc[pk] * P.Sc[pk]) continue;
+            const R rk = dev_sqrt(rk2);
+            R3<R> gj[2], gk[2];
+            if (sv.y != (R)0 || sv.z != (R)0) {
+                // bond (i -> m), environment k: m is the partner j
+                trip_grad(P, ti, pk, d, r, dk, rk, gj, gk);
+                ax -= sv.y * gj[0].x + sv.z * gj[1].x;
+                ay -= sv.y * gj[0].y + sv.z * gj[1].y;
+                az -= sv.y * gj[0].z + sv.z * gj[1].z;
+            }
+            const V4 sk = slot[(size_t)i * S.Ws + t];             // bond (i -> k)
+            if (sk.y != (R)0 || sk.z != (R)0) {
+                // bond (i -> k), environment m: m is the environment atom
+                trip_grad(P, ti, pp, dk, rk, d, r, gj, gk);
+                ax -= sk.y * gk[0].x + sk.z * gk[1].x;
+                ay -= sk.y * gk[0].y + sk.z * gk[1].y;
+                az -= sk.y * gk[0].z + sk.z * gk[1].z;
+            }
+        }
+        fx += (double)ax;
+        fy += (double)ay;
+        fz += (double)az;
+    }
+    S.Fcov[m] = fx;
+    S.Fcov[S.npad + m] = fy;
+    S.Fcov[2 * S.npad + m] = fz;
+}
+
+} // namespace ctbop
