@@ -88,6 +88,9 @@ extern "C" {
 /* flags of ctbop_compute_energy_forces_charges */
 #define CTBOP_FLAG_WARM_START    1  /* start the charge solve from the last call's charges */
 #define CTBOP_FLAG_FORCE_REBUILD 2  /* rebuild cell bins and lists regardless of motion   */
+#define CTBOP_FLAG_EXTRAPOLATE   4  /* with WARM_START: start from the quadratic (or linear)
+                                       extrapolation of the last three (two) solutions, for
+                                       consecutive MD steps; ctbop_md_run always does this  */
 
 typedef struct ctbop_ctx ctbop_ctx;
 
@@ -112,6 +115,7 @@ typedef struct {
     int    max_short;   /* largest covalent-list row at the last rebuild       */
     unsigned long long nnz_long;   /* Coulomb-list entries at the last rebuild  */
     unsigned long long nnz_short;  /* covalent-list entries at the last rebuild */
+    int    n_rebuild;   /* list rebuilds since this system buffer was set up   */
 } ctbop_info;
 
 /* Fill *o with the defaults above. */

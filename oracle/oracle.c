@@ -38,7 +38,8 @@
 /* ------------------------------------------------------------------------- */
 
 typedef struct { int j; double d[3]; double r; } pr_t;   /* neighbour entry */
-typedef struct { int n; long *off; pr_t *p; } nlist_t;   /* CSR over atoms  */
+/* CSR over rows; row k is atom rows[k] (rows == NULL: row k is atom k) */
+typedef struct { int n; long *off; pr_t *p; int *rows; } nlist_t;
 
 typedef struct {
     double h[3][3];      /* rows: cell vectors */
@@ -100,8 +101,10 @@ static void nl_free(nlist_t *L)
 {
     free(L->off);
     free(L->p);
+    free(L->rows);
     L->off = NULL;
     L->p = NULL;
+    L->rows = NULL;
 }
 
 /* Brute force: all atoms j and all images n with |n_a| <= ceil(rc/w_a) + 1
@@ -112,6 +115,7 @@ static void nl_brute(const cell_t *c, int n, const double *pos, double rc, nlist
     int M[3];
     for (int a = 0; a < 3; a++) M[a] = c->pbc[a] ? (int)ceil(rc / c->w[a]) + 1 : 0;
     L->n = n;
+    L->rows = NULL;
     L->off = calloc(n + 1, sizeof(long));
     long *cnt = calloc(n, sizeof(long));
     const double rc2 = rc * rc;
@@ -150,8 +154,9 @@ static void nl_brute(const cell_t *c, int n, const double *pos, double rc, nlist
 
 /* Cell list with cells at least rc wide and a +-1 stencil.  Needs >= 3 cells
  * along every periodic vector (returns -1 otherwise).  Along non-periodic
- * vectors the cells span the atoms' range. */
-static int nl_cells(const cell_t *c, int n, const double *pos, double rc, nlist_t *L)
+ * vectors the cells span the atoms' range.  With sel != NULL, rows are built
+ * only for the nsel atoms listed in sel. */
+static int nl_cells_sel(const cell_t *c, int n, const double *pos, double rc, nlist_t *L, const int *sel, int nsel)
 {
     double *xw = wrapped(c, n, pos);
     double *s = malloc(sizeof(double) * 3 * n);
@@ -190,14 +195,21 @@ static int nl_cells(const cell_t *c, int n, const double *pos, double rc, nlist_
     for (int i = 0; i < n; i++) members[head[cid[i]] + fill[cid[i]]++] = i;
     free(fill);
 
-    L->n = n;
-    L->off = calloc(n + 1, sizeof(long));
-    long *cnt = calloc(n, sizeof(long));
+    const int nrow = sel ? nsel : n;
+    L->n = nrow;
+    L->rows = NULL;
+    if (sel) {
+        L->rows = malloc(sizeof(int) * (nrow > 0 ? nrow : 1));
+        memcpy(L->rows, sel, sizeof(int) * nrow);
+    }
+    L->off = calloc(nrow + 1, sizeof(long));
+    long *cnt = calloc(nrow > 0 ? nrow : 1, sizeof(long));
     const double rc2 = rc * rc;
     for (int pass = 0; pass < 2; pass++) {
 #pragma omp parallel for schedule(dynamic, 64)
-        for (int i = 0; i < n; i++) {
-            long k = pass ? L->off[i] : 0;
+        for (int row = 0; row < nrow; row++) {
+            const int i = sel ? sel[row] : row;
+            long k = pass ? L->off[row] : 0;
             int c0 = cid[i] / (nb[1] * nb[2]), c1 = (cid[i] / nb[2]) % nb[1], c2 = cid[i] % nb[2];
             for (int d0 = -1; d0 <= 1; d0++)
                 for (int d1 = -1; d1 <= 1; d1++)
@@ -229,15 +241,20 @@ static int nl_cells(const cell_t *c, int n, const double *pos, double rc, nlist_
                             k++;
                         }
                     }
-            if (!pass) cnt[i] = k;
+            if (!pass) cnt[row] = k;
         }
         if (!pass) {
-            for (int i = 0; i < n; i++) L->off[i + 1] = L->off[i] + cnt[i];
-            L->p = malloc(sizeof(pr_t) * (L->off[n] > 0 ? L->off[n] : 1));
+            for (int r = 0; r < nrow; r++) L->off[r + 1] = L->off[r] + cnt[r];
+            L->p = malloc(sizeof(pr_t) * (L->off[nrow] > 0 ? L->off[nrow] : 1));
         }
     }
     free(cnt); free(members); free(head); free(cid); free(s); free(xw);
     return 0;
+}
+
+static int nl_cells(const cell_t *c, int n, const double *pos, double rc, nlist_t *L)
+{
+    return nl_cells_sel(c, n, pos, rc, L, NULL, 0);
 }
 
 /* method: 0 = brute force, 1 = cell list, -1 = cell list when it applies and
@@ -255,6 +272,11 @@ static void nl_filter(const nlist_t *A, double rc, nlist_t *B)
 {
     int n = A->n;
     B->n = n;
+    B->rows = NULL;
+    if (A->rows) {
+        B->rows = malloc(sizeof(int) * (n > 0 ? n : 1));
+        memcpy(B->rows, A->rows, sizeof(int) * n);
+    }
     B->off = calloc(n + 1, sizeof(long));
     for (int i = 0; i < n; i++) {
         long k = 0;
@@ -471,14 +493,21 @@ int oracle_sample(int n, const double *pos, const int *types, const double *box,
     const double rs = short_cut(&P);
     const double rclu = fmax(P.rc, 2.0 * rs + 1e-6);
     nlist_t L;
-    nl_build(&c, n, pos, rclu, -1, &L);
+    /* rows only for the sampled atoms (cell list), or all rows (brute force) */
+    int *rowof = malloc(sizeof(int) * (ns > 0 ? ns : 1));
+    if (nl_cells_sel(&c, n, pos, rclu, &L, idx, ns) == 0) {
+        for (int s = 0; s < ns; s++) rowof[s] = s;
+    } else {
+        nl_brute(&c, n, pos, rclu, &L);
+        for (int s = 0; s < ns; s++) rowof[s] = idx[s];
+    }
     for (int s = 0; s < ns; s++) {
-        int i = idx[s];
+        int i = idx[s], row = rowof[s];
         const sp_t_r *si = &P.sp[types[i]];
         double gi = si->chi + si->J * q[i], f[3] = {0, 0, 0};
         double ei = si->E0 + si->chi * q[i] + 0.5 * si->J * q[i] * q[i];
         int m = 1;
-        for (long e = L.off[i]; e < L.off[i + 1]; e++) {
+        for (long e = L.off[row]; e < L.off[row + 1]; e++) {
             const pr_t *p = &L.p[e];
             if (p->r < P.rc) {
                 double dC, Cv = coul_r(&P, types[i], types[p->j], p->r, &dC);
@@ -495,7 +524,7 @@ int oracle_sample(int n, const double *pos, const int *types, const double *box,
         cp[0] = cp[1] = cp[2] = 0.0;
         ct[0] = types[i];
         int k = 1;
-        for (long e = L.off[i]; e < L.off[i + 1]; e++)
+        for (long e = L.off[row]; e < L.off[row + 1]; e++)
             if (L.p[e].r < 2.0 * rs + 1e-6) {
                 memcpy(cp + 3 * k, L.p[e].d, 3 * sizeof(double));
                 ct[k++] = types[L.p[e].j];
@@ -515,12 +544,13 @@ int oracle_sample(int n, const double *pos, const int *types, const double *box,
         free(ea); free(Fc); free(cp); free(ct);
         nl_free(&Lc);
     }
+    free(rowof);
     nl_free(&L);
     return 0;
 }
 
-/* Total energy at given charges, streamed per atom without storing the long
- * list (for inputs too large for oracle_eval's memory). */
+/* Total energy at given charges, streamed over chunks of atoms so the long
+ * list never exists whole (for inputs too large for oracle_eval's memory). */
 double oracle_energy_at_q(int n, const double *pos, const int *types, const double *box,
                           const int *pbc, const double *params, const double *q, double *eat)
 {
@@ -528,15 +558,31 @@ double oracle_energy_at_q(int n, const double *pos, const int *types, const doub
     read_params_r(params, -1, 0.0, &P);
     cell_t c;
     cell_init(&c, box, pbc);
-    nlist_t Ls;
-    nl_build(&c, n, pos, short_cut(&P), -1, &Ls);
     double *ea = calloc(n, sizeof(double));
-    covalent_r(&P, n, types, &Ls, ea, NULL);
-    nl_free(&Ls);
-    nlist_t Ll;
-    nl_build(&c, n, pos, P.rc, -1, &Ll);
-    charge_terms_r(&P, n, types, &Ll, q, ea, NULL);
-    nl_free(&Ll);
+    const int chunk = 65536;
+    int *sel = malloc(sizeof(int) * chunk);
+    for (int a = 0; a < n; a += chunk) {
+        int m = (n - a < chunk) ? n - a : chunk;
+        for (int k = 0; k < m; k++) sel[k] = a + k;
+        nlist_t Ll, Ls;
+        if (nl_cells_sel(&c, n, pos, P.rc, &Ll, sel, m) != 0) {
+            /* small periodic cell: whole brute-force list */
+            nl_brute(&c, n, pos, P.rc, &Ll);
+            nl_filter(&Ll, short_cut(&P), &Ls);
+            covalent_r(&P, n, types, &Ls, ea, NULL);
+            charge_terms_r(&P, n, types, &Ll, q, ea, NULL);
+            nl_free(&Ll); nl_free(&Ls);
+            break;
+        }
+        nl_filter(&Ll, short_cut(&P), &Ls);
+        double *tmp = calloc(n, sizeof(double));
+        covalent_r(&P, n, types, &Ls, tmp, NULL);
+        for (int k = 0; k < m; k++) ea[a + k] = tmp[a + k];
+        free(tmp);
+        charge_terms_r(&P, n, types, &Ll, q, ea, NULL);
+        nl_free(&Ll); nl_free(&Ls);
+    }
+    free(sel);
     double E = 0.0;
     for (int i = 0; i < n; i++) E += ea[i];
     if (eat) memcpy(eat, ea, sizeof(double) * n);

@@ -198,11 +198,13 @@ static SC FN(covalent)(const FN(prm_t) *P, int n, const int *types, const nlist_
                        SC *eat, SC *F)
 {
     SC Etot = 0.0;
-    for (int i = 0; i < n; i++) {
+    (void)n;
+    for (int row = 0; row < L->n; row++) {
+        const int i = L->rows ? L->rows[row] : row;
         const int ti = types[i];
         const FN(sp_t) *si = &P->sp[ti];
         SC ei = 0.0;
-        for (long e = L->off[i]; e < L->off[i + 1]; e++) {
+        for (long e = L->off[row]; e < L->off[row + 1]; e++) {
             const int j = L->p[e].j;
             const double r = L->p[e].r;
             FN(pair_t) pj = FN(pair_params)(P, ti, types[j]);
@@ -211,7 +213,7 @@ static SC FN(covalent)(const FN(prm_t) *P, int n, const int *types, const nlist_
             double u[3] = {dv[0] / r, dv[1] / r, dv[2] / r};
             /* environment sums zeta_l (Eq. 2, one per channel) */
             SC z[2] = {0.0, 0.0};
-            for (long e2 = L->off[i]; e2 < L->off[i + 1]; e2++) {
+            for (long e2 = L->off[row]; e2 < L->off[row + 1]; e2++) {
                 if (e2 == e) continue;
                 const int k = L->p[e2].j;
                 const double rk = L->p[e2].r;
@@ -237,7 +239,7 @@ static SC FN(covalent)(const FN(prm_t) *P, int n, const int *types, const nlist_
             }
             /* bond-order part: P_l = dV/dzeta_l = -1/2 fc fA db/dzeta_l */
             SC Pl[2] = {-0.5 * f * fA * db[0], -0.5 * f * fA * db[1]};
-            for (long e2 = L->off[i]; e2 < L->off[i + 1]; e2++) {
+            for (long e2 = L->off[row]; e2 < L->off[row + 1]; e2++) {
                 if (e2 == e) continue;
                 const int k = L->p[e2].j;
                 const double rk = L->p[e2].r;
@@ -395,10 +397,12 @@ static SC FN(charge_terms)(const FN(prm_t) *P, int n, const int *types, const nl
                            const SC *q, SC *eat, SC *F)
 {
     SC Etot = 0.0;
-    for (int i = 0; i < n; i++) {
+    (void)n;
+    for (int row = 0; row < L->n; row++) {
+        const int i = L->rows ? L->rows[row] : row;
         const FN(sp_t) *s = &P->sp[types[i]];
         SC ei = s->E0 + s->chi * q[i] + 0.5 * s->J * q[i] * q[i];
-        for (long e = L->off[i]; e < L->off[i + 1]; e++) {
+        for (long e = L->off[row]; e < L->off[row + 1]; e++) {
             const int j = L->p[e].j;
             SC dC;
             SC Cv = FN(coul)(P, types[i], types[j], L->p[e].r, &dC);

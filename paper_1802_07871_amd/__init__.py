@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libctbop.so")
 N_PARAMS = 56
 
 OK, E_INVAL, E_NOMEM, E_TOO_CLOSE, E_QEQ_NOCONV, E_QEQ_NOT_PD, E_NEIGH_OVERFLOW, E_HIP, E_BUSY = range(9)
-FLAG_WARM_START, FLAG_FORCE_REBUILD = 1, 2
+FLAG_WARM_START, FLAG_FORCE_REBUILD, FLAG_EXTRAPOLATE = 1, 2, 4
 _CODES = {1: "E_INVAL", 2: "E_NOMEM", 3: "E_TOO_CLOSE", 4: "E_QEQ_NOCONV", 5: "E_QEQ_NOT_PD",
           6: "E_NEIGH_OVERFLOW", 7: "E_HIP", 8: "E_BUSY"}
 
@@ -43,7 +43,7 @@ class Info(ctypes.Structure):
     _fields_ = [("energy", ctypes.c_double), ("cg_residual", ctypes.c_double), ("mu", ctypes.c_double),
                 ("cg_iters", ctypes.c_int), ("rebuilt", ctypes.c_int), ("status", ctypes.c_int),
                 ("max_long", ctypes.c_int), ("max_short", ctypes.c_int),
-                ("nnz_long", ctypes.c_ulonglong), ("nnz_short", ctypes.c_ulonglong)]
+                ("nnz_long", ctypes.c_ulonglong), ("nnz_short", ctypes.c_ulonglong), ("n_rebuild", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -210,7 +210,8 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
     size_t o_ecov = take(8 * np), o_fcov = take(8 * 3 * np);
     size_t o_q = take(8 * np), o_r = take(8 * np), o_p = take(8 * np), o_s = take(8 * np), o_d = take(8 * np),
            o_jd = take(8 * np);
-    size_t o_qs = take(8 * (size_t)n), o_part = take(8 * NPART * (size_t)S.ntile);
+    size_t o_qs = take(8 * (size_t)n), o_qh1 = take(8 * (size_t)n), o_qh2 = take(8 * (size_t)n);
+    size_t o_part = take(8 * NPART * (size_t)S.ntile);
     L.bytes = o;
     L.ntile = S.ntile;
     if (base) {
@@ -239,6 +240,8 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
         S.dinv = (double *)(base + o_d);
         S.jd = (double *)(base + o_jd);
         S.q_state = (double *)(base + o_qs);
+        S.q_h1 = (double *)(base + o_qh1);
+        S.q_h2 = (double *)(base + o_qh2);
         S.part = (double *)(base + o_part);
         S.sst = (SegState *)(base + L.off_sst);
     }
@@ -382,36 +385,40 @@ template <typename R>
 int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *iters_out)
 {
     const int nt = P.L.ntile;
-    const dim3 g(nt), b(TILE);
+    const dim3 g(nt), b(TILE), g1(1);
     hipStream_t st = P.st;
     const int force = (flags & CTBOP_FLAG_FORCE_REBUILD) || P.fresh;
-    const int warm = (flags & CTBOP_FLAG_WARM_START) && !P.fresh;
-    hipLaunchKernelGGL(k_call_init, dim3(1), dim3(64), 0, st, P.dseg, 1, force);
+    int warm = 0;
+    if ((flags & CTBOP_FLAG_WARM_START) && !P.fresh) warm = (flags & CTBOP_FLAG_EXTRAPOLATE) ? 2 : 1;
+    const int *sid = P.dsegid;
+    hipLaunchKernelGGL(k_call_init, g1, dim3(64), 0, st, P.dseg, 1, force);
     hipLaunchKernelGGL(k_check_disp, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_bin_clear, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_bin, g, b, 0, st, P.dtiles, P.dseg);
-    hipLaunchKernelGGL(k_scan, dim3(1), b, 0, st, P.dsegid, P.dseg);
+    hipLaunchKernelGGL(k_scan, g1, b, 0, st, sid, P.dseg);
     hipLaunchKernelGGL(k_scatter, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_cell_sort, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_gather<R>, g, b, 0, st, P.dtiles, P.dseg, warm);
+    hipLaunchKernelGGL(k_fin_qshift, g1, b, 0, st, sid, P.dseg);
     hipLaunchKernelGGL(k_qfix, g, b, 0, st, P.dtiles, P.dseg);
     {
         Timed t(ctx, 7, st);
         hipLaunchKernelGGL(k_build<R>, g, b, 0, st, P.dtiles, P.dseg, prm);
     }
     hipLaunchKernelGGL(k_rev, g, b, 0, st, P.dtiles, P.dseg);
-    hipLaunchKernelGGL(k_mark_built, dim3(1), dim3(64), 0, st, P.dseg, 1);
+    hipLaunchKernelGGL(k_mark_built, g1, dim3(64), 0, st, P.dseg, 1);
     {
         Timed t(ctx, 3, st);
-        hipLaunchKernelGGL((k_bond<R>), g, b, 0, st, P.dtiles, P.dseg, prm, ctx->pd);
+        hipLaunchKernelGGL((k_bond<R>), g, b, 0, st, P.dtiles, P.dseg, ctx->pd);
     }
     CgCtl ctl{ctx->opts.cg_tol, ctx->opts.cg_maxit};
     {
         Timed t(ctx, 2, st);
-        hipLaunchKernelGGL((k_assemble<R, LPR>), g, b, 0, st, P.dtiles, P.dseg, prm, ctx->pd, ctl);
+        hipLaunchKernelGGL((k_assemble<R, LPR>), g, b, 0, st, P.dtiles, P.dseg, ctx->pd);
     }
+    hipLaunchKernelGGL(k_fin_assemble, g1, b, 0, st, sid, P.dseg, ctl);
     HIPCHK(hipGetLastError());
-    // charge solve: launch iterations in chunks, then read the convergence flag
+    // charge solve: launch iterations in batches, then read the convergence flag
     int done_it = 0;
     int chunk = std::max(ctx->opts.cg_check, std::min(ctx->last_iters[P.base], ctx->opts.cg_maxit));
     for (;;) {
@@ -422,12 +429,14 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
             }
             {
                 Timed t(ctx, 0, st);
-                hipLaunchKernelGGL((k_spmv<R, LPR>), g, b, 0, st, P.dtiles, P.dseg, prm);
+                hipLaunchKernelGGL((k_spmv<R, LPR>), g, b, 0, st, P.dtiles, P.dseg);
             }
+            hipLaunchKernelGGL(k_fin_alpha, g1, b, 0, st, sid, P.dseg);
             {
                 Timed t(ctx, 5, st);
-                hipLaunchKernelGGL(k_cg_update, g, b, 0, st, P.dtiles, P.dseg, ctl);
+                hipLaunchKernelGGL(k_cg_update, g, b, 0, st, P.dtiles, P.dseg);
             }
+            hipLaunchKernelGGL(k_fin_update, g1, b, 0, st, sid, P.dseg, ctl);
         }
         done_it += chunk;
         HIPCHK(hipGetLastError());
@@ -445,8 +454,9 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
     }
     {
         Timed t(ctx, 1, st);
-        hipLaunchKernelGGL((k_force_coul<R, LPR>), g, b, 0, st, P.dtiles, P.dseg, prm, ctx->pd);
+        hipLaunchKernelGGL((k_force_coul<R, LPR>), g, b, 0, st, P.dtiles, P.dseg, ctx->pd);
     }
+    hipLaunchKernelGGL(k_fin_energy, g1, b, 0, st, sid, P.dseg);
     HIPCHK(hipGetLastError());
     return CTBOP_OK;
 }
@@ -473,6 +483,7 @@ int fill_info(ctbop_ctx *ctx, Prep &P, ctbop_info *info)
     info->max_short = ss.maxs;
     info->nnz_long = ss.nnz_long;
     info->nnz_short = ss.nnz_short;
+    info->n_rebuild = ss.nrebuild;
     if (ss.status) return fail(info->status, status_text(ss.status));
     return CTBOP_OK;
 }
@@ -602,15 +613,18 @@ int ctbop_md_run(ctbop_ctx *ctx, int n, double *x, double *v, const int32_t *typ
     const dim3 g(P.L.ntile), b(TILE);
     int iters = 0, status_acc = 0;
     // forces at the start
-    rc = eval_any(ctx, P, CTBOP_FLAG_WARM_START, &iters);
+    const int mdflags = CTBOP_FLAG_WARM_START | CTBOP_FLAG_EXTRAPOLATE;
+    rc = eval_any(ctx, P, mdflags, &iters);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_md_kick, g, b, 0, P.st, P.dtiles, P.dseg, MdIO{x, v, F, fixed, 0.0, {io.mass[0], io.mass[1]}}, P.dke);
+    hipLaunchKernelGGL(k_md_kick, g, b, 0, P.st, P.dtiles, P.dseg, MdIO{x, v, F, fixed, 0.0, {io.mass[0], io.mass[1]}});
+    hipLaunchKernelGGL(k_fin_ke, dim3(1), b, 0, P.st, P.dsegid, P.dseg, P.dke);
     for (int s = 0; s <= nsteps; s++) {
         if (s > 0) {
             hipLaunchKernelGGL(k_md_kick_drift, g, b, 0, P.st, P.dtiles, P.dseg, io);
-            rc = eval_any(ctx, P, CTBOP_FLAG_WARM_START, &iters);
+            rc = eval_any(ctx, P, mdflags, &iters);
             if (rc) return rc;
-            hipLaunchKernelGGL(k_md_kick, g, b, 0, P.st, P.dtiles, P.dseg, io, P.dke);
+            hipLaunchKernelGGL(k_md_kick, g, b, 0, P.st, P.dtiles, P.dseg, io);
+            hipLaunchKernelGGL(k_fin_ke, dim3(1), b, 0, P.st, P.dsegid, P.dseg, P.dke);
             HIPCHK(hipGetLastError());
         }
         if (thermo && s % every == 0) {

@@ -57,6 +57,8 @@ struct SegState {
     int status;        // ST_* bits, sticky until the next rebuild/call reset
     int maxl, maxs;    // largest list rows at the last build
     int built;         // lists exist
+    int nhist;         // charge solutions kept for the starting-charge predictor (0..3)
+    int nrebuild;      // rebuilds since the system buffer was set up
     double w;          // current residual shift
     double rho, alpha, beta, res;
     double sdinv;      // sum of 1/diag
@@ -110,7 +112,8 @@ struct Seg {
     double *ecov;      // [npad]
     double *Fcov;      // SoA [3 npad]
     double *q, *r, *p, *s, *dinv, *jd;   // [npad]
-    double *q_state;   // user order charges kept for the warm start [n]
+    double *q_state;   // user order charges of the last solve, for the warm start [n]
+    double *q_h1, *q_h2;   // the two solves before it (predictor history) [n]
     double *part;      // [ntile * NPART]
     SegState *sst;
 };
@@ -175,35 +178,31 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double *lds /* 4*K */,
     __syncthreads();
 }
 
-// Write this tile's K partial sums, and return true in the block that
-// completes the segment (its last tile to finish).  In that block every thread
-// may then read all partials of the segment.
+// Block sum of K values, written as this tile's partial sums.  Every kernel
+// that reduces writes partials this way; a finalize kernel (one block per
+// segment, launched next on the same stream) adds them up.  The kernel
+// boundary makes the partials visible, so no block needs a device-scope fence.
 template <int K>
-__device__ __forceinline__ bool tile_commit(const Seg &S, int tile_local, const double (&part)[K], int *is_last_lds)
+__device__ __forceinline__ void tile_partials(const Seg &S, int tile_local, double (&v)[K], double *lds)
 {
+    double tot[K];
+    block_sum<K>(v, lds, tot);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < K; k++) S.part[tile_local * NPART + k] = part[k];
-        __threadfence();
-        int t = atomicAdd(&S.sst->ticket, 1);
-        *is_last_lds = (t == S.ntile - 1);
+        for (int k = 0; k < K; k++) S.part[(size_t)tile_local * NPART + k] = tot[k];
     }
-    __syncthreads();
-    bool last = *is_last_lds;
-    if (last) __threadfence();
-    return last;
 }
 
-// Sum partial k over the segment's tiles in a fixed order (called by all 256
-// threads of the last block; result valid in thread 0).
+// Sum partial k over the segment's tiles in a fixed order (all 256 threads of
+// the finalize block; result valid in thread 0).
 template <int K>
-__device__ __forceinline__ void segment_total(const Seg &S, double *lds, double (&out)[K])
+__device__ __forceinline__ void seg_total(const Seg &S, double *lds, double (&out)[K])
 {
     double v[K];
 #pragma unroll
     for (int k = 0; k < K; k++) v[k] = 0.0;
     for (int t = threadIdx.x; t < S.ntile; t += TILE) {
-        const volatile double *pp = S.part + (size_t)t * NPART;
+        const double *pp = S.part + (size_t)t * NPART;
 #pragma unroll
         for (int k = 0; k < K; k++) v[k] += pp[k];
     }

@@ -186,8 +186,10 @@ __global__ void k_cell_sort(const Tile *tiles, Seg *segs)
     }
 }
 
-// local coordinates of every sorted atom for this call's positions, and the
-// warm-start charges in the sorted frame (with their sum, for the projection)
+// Local coordinates of every sorted atom for this call's positions, and the
+// starting charges in the sorted frame (with their sum, for the projection).
+// warm: 0 = zeros, 1 = the last solution, 2 = extrapolate the last solutions
+// (quadratic through three, linear through two), for consecutive MD steps.
 template <typename R>
 __global__ void k_gather(const Tile *tiles, Seg *segs, int warm)
 {
@@ -210,23 +212,19 @@ __global__ void k_gather(const Tile *tiles, Seg *segs, int warm)
         v.w = (R)w.w;
         reinterpret_cast<V4 *>(S.xs)[s] = v;
         if ((void *)S.xs64 != S.xs) S.xs64[s] = w;
-        q0 = warm ? S.q_state[i] : 0.0;
+        if (warm) {
+            const int nh = warm == 2 ? S.sst->nhist : 1;
+            if (nh >= 3) q0 = 3.0 * S.q_state[i] - 3.0 * S.q_h1[i] + S.q_h2[i];
+            else if (nh == 2) q0 = 2.0 * S.q_state[i] - S.q_h1[i];
+            else if (nh == 1) q0 = S.q_state[i];
+        }
         S.q[s] = q0;
     } else if (s < S.npad) {
         S.q[s] = 0.0;
     }
     __shared__ double lds[4];
-    __shared__ int last;
-    double v1[1] = {q0}, o1[1];
-    block_sum<1>(v1, lds, o1);
-    if (tile_commit<1>(S, T.row0 / TILE, o1, &last)) {
-        double tot[1];
-        segment_total<1>(S, lds, tot);
-        if (threadIdx.x == 0) {
-            S.sst->qshift = (S.Q - tot[0]) / S.n;
-            S.sst->ticket = 0;
-        }
-    }
+    double v1[1] = {q0};
+    tile_partials<1>(S, T.row0 / TILE, v1, lds);
 }
 
 // apply the projection of the starting charges onto sum q = Q
@@ -236,6 +234,15 @@ __global__ void k_qfix(const Tile *tiles, Seg *segs)
     const Seg &S = segs[T.seg];
     const int s = T.row0 + threadIdx.x;
     if (s < S.n) S.q[s] += S.sst->qshift;
+}
+
+__global__ void k_fin_qshift(const int *seg_ids, Seg *segs)
+{
+    const Seg &S = segs[seg_ids[blockIdx.x]];
+    __shared__ double lds[4];
+    double tot[1];
+    seg_total<1>(S, lds, tot);
+    if (threadIdx.x == 0) S.sst->qshift = (S.Q - tot[0]) / S.n;
 }
 
 // table of D(code) for the block's segment, in LDS
@@ -347,7 +354,10 @@ __global__ void k_rev(const Tile *tiles, Seg *segs)
 __global__ void k_mark_built(Seg *segs, int nseg)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < nseg && segs[k].sst->rebuild) segs[k].sst->built = 1;
+    if (k < nseg && segs[k].sst->rebuild) {
+        segs[k].sst->built = 1;
+        segs[k].sst->nrebuild += 1;
+    }
 }
 
 } // namespace ctbop

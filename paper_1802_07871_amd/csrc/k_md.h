@@ -34,13 +34,12 @@ __global__ void __launch_bounds__(TILE) k_md_kick_drift(const Tile *tiles, Seg *
     }
 }
 
-// second half kick and the kinetic energy (deterministic per-segment sum)
-__global__ void __launch_bounds__(TILE) k_md_kick(const Tile *tiles, Seg *segs, MdIO io, double *ke_out)
+// second half kick and the tile's kinetic energy
+__global__ void __launch_bounds__(TILE) k_md_kick(const Tile *tiles, Seg *segs, MdIO io)
 {
     const Tile T = tiles[blockIdx.x];
     const Seg &S = segs[T.seg];
     __shared__ double lds[4];
-    __shared__ int last;
     const int i = T.row0 + threadIdx.x;
     double ke = 0.0;
     if (i < S.n) {
@@ -57,15 +56,20 @@ __global__ void __launch_bounds__(TILE) k_md_kick(const Tile *tiles, Seg *segs, 
             ke += 0.5 * m * v * v / ACC_UNIT;
         }
     }
-    double v1[1] = {ke}, tot[1];
-    block_sum<1>(v1, lds, tot);
-    if (tile_commit<1>(S, T.row0 / TILE, tot, &last)) {
-        segment_total<1>(S, lds, tot);
-        if (threadIdx.x == 0) {
-            ke_out[0] = tot[0];
-            ke_out[1] = S.sst->energy;
-            S.sst->ticket = 0;
-        }
+    double v1[1] = {ke};
+    tile_partials<1>(S, T.row0 / TILE, v1, lds);
+}
+
+// kinetic and potential energy of the step
+__global__ void k_fin_ke(const int *seg_ids, Seg *segs, double *ke_out)
+{
+    const Seg &S = segs[seg_ids[blockIdx.x]];
+    __shared__ double lds[4];
+    double tot[1];
+    seg_total<1>(S, lds, tot);
+    if (threadIdx.x == 0) {
+        ke_out[0] = tot[0];
+        ke_out[1] = S.sst->energy;
     }
 }
 

@@ -60,15 +60,13 @@ struct CgCtl {
 // Assemble the Coulomb entries of every row, the diagonal (J plus self
 // images) and the starting residual r = -(H q0 + chi) + mu_prev.
 template <typename R, int LPR>
-__global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs, Params<R> P, Params<double> PD,
-                                                   CgCtl ctl)
+__global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs, Params<double> PD)
 {
     using V4 = typename Vec4<R>::type;
     const Tile T = tiles[blockIdx.x];
     const Seg &S = segs[T.seg];
     __shared__ V4 dtab[NCODE];
     __shared__ double lds[4 * 5];
-    __shared__ int last;
     load_dtab2<R>(S, dtab);
     const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
     R *H = reinterpret_cast<R *>(S.H);
@@ -100,11 +98,10 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
         self = group_sum<LPR>(self);
         if (lane == 0) {
             const double qs = S.q[s];
-            const double dg = P.J[ti] + self;
-            const double di = 1.0 / dg;
-            const double r = -(P.J[ti] * qs + acc + P.chi[ti]) + mprev;
+            const double di = 1.0 / (PD.J[ti] + self);
+            const double r = -(PD.J[ti] * qs + acc + PD.chi[ti]) + mprev;
             S.dinv[s] = di;
-            S.jd[s] = P.J[ti];
+            S.jd[s] = PD.J[ti];
             S.r[s] = r;
             S.p[s] = 0.0;
             acc5[0] += r * di;
@@ -114,25 +111,28 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
             acc5[4] += di;
         }
     }
+    tile_partials<5>(S, T.row0 / TILE, acc5, lds);
+}
+
+__global__ void k_fin_assemble(const int *seg_ids, Seg *segs, CgCtl ctl)
+{
+    const Seg &S = segs[seg_ids[blockIdx.x]];
+    __shared__ double lds[4 * 5];
     double tot[5];
-    block_sum<5>(acc5, lds, tot);
-    if (tile_commit<5>(S, T.row0 / TILE, tot, &last)) {
-        segment_total<5>(S, lds, tot);
-        if (threadIdx.x == 0) {
-            SegState *st = S.sst;
-            const double w = tot[0] / tot[4];
-            const double res2 = (tot[3] - tot[2] * tot[2] / S.n) / S.n;
-            st->sdinv = tot[4];
-            st->w = w;
-            st->rho = tot[1] - w * tot[0];
-            st->beta = 0.0;
-            st->res = sqrt(fmax(res2, 0.0));
-            st->mshift = mprev - w;
-            st->iters = 0;
-            st->qshift = 0.0;
-            st->done = (st->res < ctl.tol) ? 1 : 0;
-            st->ticket = 0;
-        }
+    seg_total<5>(S, lds, tot);
+    if (threadIdx.x == 0) {
+        SegState *st = S.sst;
+        const double w = tot[0] / tot[4];
+        const double res2 = (tot[3] - tot[2] * tot[2] / S.n) / S.n;
+        st->sdinv = tot[4];
+        st->w = w;
+        st->rho = tot[1] - w * tot[0];
+        st->beta = 0.0;
+        st->res = sqrt(fmax(res2, 0.0));
+        st->mshift = st->mu_prev - w;
+        st->iters = 0;
+        st->qshift = 0.0;
+        st->done = (st->res < ctl.tol) ? 1 : 0;
     }
 }
 
@@ -150,15 +150,14 @@ __global__ void __launch_bounds__(TILE) k_cg_dir(const Tile *tiles, Seg *segs)
     S.p[s] = S.dinv[s] * r + beta * S.p[s];
 }
 
-// s = H p and p^T s; the segment's last block sets alpha = rho / p^T H p
+// s = H p and the tile's share of p^T s
 template <typename R, int LPR>
-__global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs, Params<R> P)
+__global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
 {
     const Tile T = tiles[blockIdx.x];
     const Seg &S = segs[T.seg];
     if (S.sst->done) return;
     __shared__ double lds[4];
-    __shared__ int last;
     const R *H = reinterpret_cast<const R *>(S.H);
     constexpr int G = TILE / LPR;
     const int lane = threadIdx.x % LPR;
@@ -179,36 +178,40 @@ __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs, Par
             pap += ps * y;
         }
     }
-    double v[1] = {pap}, tot[1];
-    block_sum<1>(v, lds, tot);
-    if (tile_commit<1>(S, T.row0 / TILE, tot, &last)) {
-        segment_total<1>(S, lds, tot);
-        if (threadIdx.x == 0) {
-            SegState *st = S.sst;
-            if (!(tot[0] > 0.0)) {
-                st->status |= ST_NOT_PD;
-                st->done = 1;
-                st->alpha = 0.0;
-            } else {
-                st->alpha = st->rho / tot[0];
-            }
-            st->ticket = 0;
+    double v[1] = {pap};
+    tile_partials<1>(S, T.row0 / TILE, v, lds);
+}
+
+// alpha = rho / p^T H p
+__global__ void k_fin_alpha(const int *seg_ids, Seg *segs)
+{
+    const Seg &S = segs[seg_ids[blockIdx.x]];
+    if (S.sst->done) return;
+    __shared__ double lds[4];
+    double tot[1];
+    seg_total<1>(S, lds, tot);
+    if (threadIdx.x == 0) {
+        SegState *st = S.sst;
+        if (!(tot[0] > 0.0)) {
+            st->status |= ST_NOT_PD;
+            st->done = 1;
+            st->alpha = 0.0;
+        } else {
+            st->alpha = st->rho / tot[0];
         }
     }
 }
 
-// q += alpha p, r -= alpha s; the last block forms w, rho, beta and tests
-// the projected residual
-__global__ void __launch_bounds__(TILE) k_cg_update(const Tile *tiles, Seg *segs, CgCtl ctl)
+// q += alpha p, r -= alpha s, and the tile's sums for w, rho and the test
+__global__ void __launch_bounds__(TILE) k_cg_update(const Tile *tiles, Seg *segs)
 {
     const Tile T = tiles[blockIdx.x];
     const Seg &S = segs[T.seg];
     if (S.sst->done) return;
-    __shared__ double lds[4 * 6];
-    __shared__ int last;
+    __shared__ double lds[4 * 5];
     const int s = T.row0 + threadIdx.x;
     const double alpha = S.sst->alpha;
-    double v[6] = {0, 0, 0, 0, 0, 0};
+    double v[5] = {0, 0, 0, 0, 0};
     if (s < S.n) {
         const double q = S.q[s] + alpha * S.p[s];
         const double r = S.r[s] - alpha * S.s[s];
@@ -221,43 +224,48 @@ __global__ void __launch_bounds__(TILE) k_cg_update(const Tile *tiles, Seg *segs
         v[3] = r * r;
         v[4] = q;
     }
-    double tot[6];
-    block_sum<6>(v, lds, tot);
-    if (tile_commit<6>(S, T.row0 / TILE, tot, &last)) {
-        segment_total<6>(S, lds, tot);
-        if (threadIdx.x == 0) {
-            SegState *st = S.sst;
-            const double w = tot[0] / st->sdinv;
-            const double rho = tot[1] - w * tot[0];
-            const double res2 = (tot[3] - tot[2] * tot[2] / S.n) / S.n;
-            st->beta = rho / st->rho;
-            st->rho = rho;
-            st->w = w;
-            st->mshift -= w;
-            st->res = sqrt(fmax(res2, 0.0));
-            st->iters += 1;
-            st->qshift = (S.Q - tot[4]) / S.n;
-            if (st->res < ctl.tol) st->done = 1;
-            else if (st->iters >= ctl.maxit) { st->done = 1; st->status |= ST_NOCONV; }
-            st->ticket = 0;
-        }
+    tile_partials<5>(S, T.row0 / TILE, v, lds);
+}
+
+// w, rho, beta, the projected residual and the stop test
+__global__ void k_fin_update(const int *seg_ids, Seg *segs, CgCtl ctl)
+{
+    const Seg &S = segs[seg_ids[blockIdx.x]];
+    if (S.sst->done) return;
+    __shared__ double lds[4 * 5];
+    double tot[5];
+    seg_total<5>(S, lds, tot);
+    if (threadIdx.x == 0) {
+        SegState *st = S.sst;
+        const double w = tot[0] / st->sdinv;
+        const double rho = tot[1] - w * tot[0];
+        const double res2 = (tot[3] - tot[2] * tot[2] / S.n) / S.n;
+        st->beta = rho / st->rho;
+        st->rho = rho;
+        st->w = w;
+        st->mshift -= w;
+        st->res = sqrt(fmax(res2, 0.0));
+        st->iters += 1;
+        st->qshift = (S.Q - tot[4]) / S.n;
+        if (st->res < ctl.tol) st->done = 1;
+        else if (st->iters >= ctl.maxit) { st->done = 1; st->status |= ST_NOCONV; }
     }
 }
 
 // Coulomb forces and energy at the equilibrated charges, plus the covalent
-// forces and energies: writes F, q (user order) and the total energy.
+// forces and energies: writes F, q (user order) and the tile's energy.
 template <typename R, int LPR>
-__global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *segs, Params<R> P, Params<double> PD)
+__global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *segs, Params<double> PD)
 {
     using V4 = typename Vec4<R>::type;
     const Tile T = tiles[blockIdx.x];
     const Seg &S = segs[T.seg];
     __shared__ V4 dtab[NCODE];
     __shared__ double lds[4];
-    __shared__ int last;
     load_dtab2<R>(S, dtab);
     const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
     const double qsh = S.sst->qshift;
+    const bool keep_hist = S.q_h1 != nullptr;
     constexpr int G = TILE / LPR;
     const int lane = threadIdx.x % LPR;
     double esum = 0.0;
@@ -298,21 +306,30 @@ __global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *seg
             S.F[S.n + i] = qs * fy + S.Fcov[S.npad + s];
             S.F[2 * S.n + i] = qs * fz + S.Fcov[2 * S.npad + s];
             S.q_out[i] = qs;
+            if (keep_hist) {
+                S.q_h2[i] = S.q_h1[i];
+                S.q_h1[i] = S.q_state[i];
+            }
             S.q_state[i] = qs;
-            esum += P.E0[ti] + P.chi[ti] * qs + 0.5 * P.J[ti] * qs * qs + 0.5 * qs * ec + S.ecov[s];
+            esum += PD.E0[ti] + PD.chi[ti] * qs + 0.5 * PD.J[ti] * qs * qs + 0.5 * qs * ec + S.ecov[s];
         }
     }
-    double v[1] = {esum}, tot[1];
-    block_sum<1>(v, lds, tot);
-    if (tile_commit<1>(S, T.row0 / TILE, tot, &last)) {
-        segment_total<1>(S, lds, tot);
-        if (threadIdx.x == 0) {
-            SegState *st = S.sst;
-            st->energy = tot[0];
-            if (S.E_out) *S.E_out = tot[0];
-            st->mu_prev = st->mshift;
-            st->ticket = 0;
-        }
+    double v[1] = {esum};
+    tile_partials<1>(S, T.row0 / TILE, v, lds);
+}
+
+__global__ void k_fin_energy(const int *seg_ids, Seg *segs)
+{
+    const Seg &S = segs[seg_ids[blockIdx.x]];
+    __shared__ double lds[4];
+    double tot[1];
+    seg_total<1>(S, lds, tot);
+    if (threadIdx.x == 0) {
+        SegState *st = S.sst;
+        st->energy = tot[0];
+        if (S.E_out) *S.E_out = tot[0];
+        st->mu_prev = st->mshift;
+        st->nhist = st->nhist < 3 ? st->nhist + 1 : 3;
     }
 }
 

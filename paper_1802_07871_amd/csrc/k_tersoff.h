@@ -142,81 +142,65 @@ __device__ __forceinline__ void load_dtab2(const Seg &S, typename Vec4<R>::type 
     __syncthreads();
 }
 
-// FP64 vector of a list entry from the FP64 local coordinates
-__device__ __forceinline__ double3 pair_vec64(const Seg &S, const double4 &a, int j, int code)
-{
-    const double4 b = S.xs64[j];
-    const int d0 = code / 49 - 3, d1 = (code / 7) % 7 - 3, d2 = code % 7 - 3;
-    double3 v;
-    v.x = (b.x - a.x) + (d0 * S.cw[0][0] + d1 * S.cw[1][0] + d2 * S.cw[2][0]);
-    v.y = (b.y - a.y) + (d0 * S.cw[0][1] + d1 * S.cw[1][1] + d2 * S.cw[2][1]);
-    v.z = (b.z - a.z) + (d0 * S.cw[0][2] + d1 * S.cw[1][2] + d2 * S.cw[2][2]);
-    return v;
-}
-
-// The environment sums (triplet work) run in the pair precision R; the bond
-// length, fc, fR, fA, b and the bond energy are then evaluated in FP64, so
-// the total energy carries no FP32 rounding of the large, cancelling fR and
-// b fA terms.
+// The bond pass runs in FP64 from the FP64 local coordinates: it is a small
+// share of the step (a few bonds per atom), and FP64 keeps the energy free of
+// FP32 rounding in zeta, b and the large, cancelling fR and b fA terms.  The
+// coefficients are stored in the pair precision R for the force gather.
 template <typename R>
-__global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Params<R> P, Params<double> PD)
+__global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Params<double> P)
 {
     using V4 = typename Vec4<R>::type;
     const Tile T = tiles[blockIdx.x];
     const Seg &S = segs[T.seg];
-    __shared__ V4 dtab[NCODE];
-    load_dtab2<R>(S, dtab);
+    __shared__ double4 dtab[NCODE];
+    load_dtab2<double>(S, dtab);
     const int s = T.row0 + threadIdx.x;
     if (s >= S.n) {
         if (s < S.npad) S.ecov[s] = 0.0;
         return;
     }
-    const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
+    const double4 *xs = S.xs64;
     V4 *slot = reinterpret_cast<V4 *>(S.slot) + (size_t)s * S.Ws;
     const uint32_t *row = S.sidx + (size_t)s * S.Ws;
-    const V4 li = xs[s];
-    const double4 li64 = S.xs64[s];
+    const double4 li = xs[s];
     const int ti = (int)li.w;
     const int ns = S.scnt[s];
     double ecov = 0.0;
     for (int e = 0; e < ns; e++) {
         const uint32_t ent = row[e];
-        const V4 lj = xs[ent & J_MASK];
+        const double4 lj = xs[ent & J_MASK];
         const int tj = (int)lj.w, pp = ti * 2 + tj;
-        const R3<R> d = pair_vec<R>(li, lj, dtab[ent >> CODE_SHIFT]);
-        const R r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+        const R3<double> d = pair_vec<double>(li, lj, dtab[ent >> CODE_SHIFT]);
+        const double r2 = d.x * d.x + d.y * d.y + d.z * d.z;
         V4 out;
         out.x = out.y = out.z = out.w = (R)0;
         if (r2 < P.Sc[pp] * P.Sc[pp]) {
-            const R r = dev_sqrt(r2);
-            R z1 = 0, z2 = 0;
+            const double r = sqrt(r2);
+            double z1 = 0, z2 = 0;
             for (int e2 = 0; e2 < ns; e2++) {
                 if (e2 == e) continue;
                 const uint32_t ent2 = row[e2];
-                const V4 lk = xs[ent2 & J_MASK];
+                const double4 lk = xs[ent2 & J_MASK];
                 const int pk = ti * 2 + (int)lk.w;
-                const R3<R> dk = pair_vec<R>(li, lk, dtab[ent2 >> CODE_SHIFT]);
-                const R rk2 = dk.x * dk.x + dk.y * dk.y + dk.z * dk.z;
+                const R3<double> dk = pair_vec<double>(li, lk, dtab[ent2 >> CODE_SHIFT]);
+                const double rk2 = dk.x * dk.x + dk.y * dk.y + dk.z * dk.z;
                 if (rk2 >= P.Sc[pk] * P.Sc[pk]) continue;
-                const R rk = dev_sqrt(rk2);
-                const R cs = (d.x * dk.x + d.y * dk.y + d.z * dk.z) / (r * rk);
-                R dummy;
-                const R fk = cutoff(rk, P.Rc[pk], P.Sc[pk], P.piSR[pk], dummy);
-                R dw, dex;
-                R w1 = angular(P, ti, 0, cs, dw), w2 = angular(P, ti, 1, cs, dw);
+                const double rk = sqrt(rk2);
+                const double cs = (d.x * dk.x + d.y * dk.y + d.z * dk.z) / (r * rk);
+                double dummy, dw, dex;
+                const double fk = cutoff<double>(rk, P.Rc[pk], P.Sc[pk], P.piSR[pk], dummy);
+                double w1 = angular<double>(P, ti, 0, cs, dw), w2 = angular<double>(P, ti, 1, cs, dw);
                 if (!P.alpha_zero[ti]) {
-                    w1 *= radial(P, ti, 0, r - rk, dex);
-                    w2 *= radial(P, ti, 1, r - rk, dex);
+                    w1 *= radial<double>(P, ti, 0, r - rk, dex);
+                    w2 *= radial<double>(P, ti, 1, r - rk, dex);
                 }
                 z1 += fk * w1;
                 z2 += fk * w2;
             }
-            const double3 d64 = pair_vec64(S, li64, (int)(ent & J_MASK), (int)(ent >> CODE_SHIFT));
-            const double rd = sqrt(d64.x * d64.x + d64.y * d64.y + d64.z * d64.z);
             double db1, db2, dfc;
-            const double b = bond_order<double>(PD, ti, (double)z1, (double)z2, db1, db2);
-            const double fc = cutoff<double>(rd, PD.Rc[pp], PD.Sc[pp], PD.piSR[pp], dfc);
-            const double fR = PD.A[pp] * exp(-PD.lam1[pp] * rd), fA = PD.B[pp] * exp(-PD.lam2[pp] * rd);
+            const double b = bond_order<double>(P, ti, z1, z2, db1, db2);
+            const double fc = cutoff<double>(r, P.Rc[pp], P.Sc[pp], P.piSR[pp], dfc);
+            const double fR = P.A[pp] * exp(-P.lam1[pp] * r), fA = P.B[pp] * exp(-P.lam2[pp] * r);
             ecov += 0.5 * fc * (fR - b * fA);
             out.x = (R)b;
             out.y = (R)(-0.5 * fc * fA * db1);

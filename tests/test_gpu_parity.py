@@ -127,8 +127,9 @@ def test_warm_start_and_determinism(ct, orc, theta):
     assert i4["rebuilt"] == 0 and i4["cg_iters"] < i1["cg_iters"]
     Eo, Fo, qo, _ = orc.evaluate(pos, s.types, s.box, s.pbc, theta, tol=1e-13)
     assert np.linalg.norm(F4.cpu().numpy() - Fo) / np.linalg.norm(Fo) < 1e-5
-    # large motion: rebuild
-    pos = s.pos + rng.normal(0, 0.3, s.pos.shape)
+    # one atom moved past half the skin: rebuild
+    pos = pos.copy()
+    pos[0] += np.array([0.3, 0.0, 0.0])
     _, F5, _, i5 = pot.compute(pos, s.types, s.box, s.pbc, warm=True)
     assert i5["rebuilt"] == 1
     Eo, Fo, qo, _ = orc.evaluate(pos, s.types, s.box, s.pbc, theta, tol=1e-13)
@@ -139,7 +140,7 @@ def test_error_codes(ct, theta):
     s = G.zincblende(2, sigma=0.0)
     print("[errors]", flush=True)
     pos = s.pos.copy()
-    pos[1] = pos[0] + 0.3
+    pos[1] = pos[0] + 0.2          # 0.35 A apart
     with pytest.raises(ct.CtbopError) as e:
         ct.Potential(theta).compute(pos, s.types, s.box, s.pbc)
     assert e.value.code == ct.E_TOO_CLOSE
