@@ -25,6 +25,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+KERNEL_SOURCES = ["ctbop_dev.h", "k_qeq.h", "k_tersoff.h", "k_lists.h", "ctbop.hip"]
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_spmv_step1m.md")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1802_07871_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic():
+    """HBM bytes per launch of the charge-solve product from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, if it was taken on the current
+    kernel sources (else None)."""
+    try:
+        txt = open(COUNTER_SUMMARY).read()
+    except OSError:
+        return None
+    for line in txt.splitlines():
+        if line.startswith("machine-readable:"):
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if kv.get("source_hash") == kernel_source_hash():
+                return float(kv["spmv_traffic_bytes_per_launch"])
+    return None
 
 
 def workload(args):
@@ -64,6 +91,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-nx", type=int, default=40)
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (scales HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (the single-system path has no multi-GPU "
@@ -77,6 +106,15 @@ def main():
     from ctbop_inputs import params as PR
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy_mb > 0:
+        nb = args.calibrate_copy_mb << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"bench: calibration copy of {nb} bytes done", file=sys.stderr, flush=True)
+        del src, dst
     theta = PR.load()
     s = workload(args)
     n = s.n
@@ -118,10 +156,13 @@ def main():
     prof = pot.profile(enable=False, reset=True)
     value = n * args.steps / dt
 
-    # dominant kernel: the charge-solve matrix-vector product
+    # dominant kernel: the charge-solve matrix-vector product.  Launches after
+    # convergence exit at once, so the average is taken over the iterations
+    # that ran (a slight overestimate of the per-launch time).
     nnz = int(info["nnz_long"])
     ms, cnt = prof["spmv"]
-    avg_s = ms / 1e3 / max(cnt, 1)
+    iters = int(info["cg_iters_total"]) - int(info_w["cg_iters_total"])
+    avg_s = ms / 1e3 / max(iters, 1)
     spmv_bytes = 8.0 * nnz + 28.0 * n          # list entry (index + value) + per-row vectors
     achieved = spmv_bytes / avg_s / 1e9
     fms, fcnt = prof["force_coul"]
@@ -147,11 +188,12 @@ def main():
                         f"30% top-Si depleted, {n} atoms, 2500 K NVE, dt 0.5 fs, charges to 1e-9 every step",
             "n_atoms": n, "cg_iters_last_step": info["cg_iters"], "nnz_long": nnz,
             "nnz_short": int(info["nnz_short"]),
-            "cg_iters_per_step": kernels["spmv"]["launches"] / args.steps,
+            "cg_iters_per_step": iters / args.steps, "list_rebuilds": int(info["n_rebuild"]) - int(info_w["n_rebuild"]),
+            "cg_res0_last_step": info["cg_res0"],
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_spmv (charge-solve H p)", "bytes_per_launch": spmv_bytes,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(),
+                     "kernel": "k_spmv (charge-solve H p)", "bytes_per_launch": spmv_bytes, "launches": iters,
                      "avg_launch_us": avg_s * 1e6},
         "roofline_force": {"bound": "hbm", "achieved": force_bytes / f_avg / 1e9 if fcnt else None,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",

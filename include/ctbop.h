@@ -116,6 +116,8 @@ typedef struct {
     unsigned long long nnz_long;   /* Coulomb-list entries at the last rebuild  */
     unsigned long long nnz_short;  /* covalent-list entries at the last rebuild */
     int    n_rebuild;   /* list rebuilds since this system buffer was set up   */
+    unsigned long long cg_iters_total;  /* charge-solve iterations since set-up */
+    double cg_res0;     /* starting RMS projected residual of the last solve   */
 } ctbop_info;
 
 /* Fill *o with the defaults above. */

@@ -43,7 +43,8 @@ class Info(ctypes.Structure):
     _fields_ = [("energy", ctypes.c_double), ("cg_residual", ctypes.c_double), ("mu", ctypes.c_double),
                 ("cg_iters", ctypes.c_int), ("rebuilt", ctypes.c_int), ("status", ctypes.c_int),
                 ("max_long", ctypes.c_int), ("max_short", ctypes.c_int),
-                ("nnz_long", ctypes.c_ulonglong), ("nnz_short", ctypes.c_ulonglong), ("n_rebuild", ctypes.c_int)]
+                ("nnz_long", ctypes.c_ulonglong), ("nnz_short", ctypes.c_ulonglong), ("n_rebuild", ctypes.c_int),
+                ("cg_iters_total", ctypes.c_ulonglong), ("cg_res0", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -24,7 +24,9 @@ using namespace ctbop;
 
 namespace {
 
-constexpr int LPR = 16;             // lanes per Coulomb-list row
+constexpr int LPR = 16;             // lanes per Coulomb-list row (assembly, force gather)
+constexpr int SPMV_LPR = 32;        // lanes per row in the charge-solve product (tuned)
+constexpr int SPMV_U = 2;           // independent entries per lane per step (tuned)
 
 thread_local std::string g_err;
 
@@ -184,7 +186,7 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
     S.npad = (n + TILE - 1) / TILE * TILE;
     S.ntile = S.npad / TILE;
     S.tile0 = 0;
-    S.Wl = ctx->opts.long_cap;
+    S.Wl = (ctx->opts.long_cap + 3) / 4 * 4;     // 16-byte aligned rows for vector loads
     S.Ws = ctx->opts.short_cap;
     S.skin = ctx->opts.skin;
     const int fp64 = ctx->opts.fp64;
@@ -429,7 +431,7 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
             }
             {
                 Timed t(ctx, 0, st);
-                hipLaunchKernelGGL((k_spmv<R, LPR>), g, b, 0, st, P.dtiles, P.dseg);
+                hipLaunchKernelGGL((k_spmv<R, SPMV_LPR, SPMV_U>), g, b, 0, st, P.dtiles, P.dseg);
             }
             hipLaunchKernelGGL(k_fin_alpha, g1, b, 0, st, sid, P.dseg);
             {
@@ -484,6 +486,8 @@ int fill_info(ctbop_ctx *ctx, Prep &P, ctbop_info *info)
     info->nnz_long = ss.nnz_long;
     info->nnz_short = ss.nnz_short;
     info->n_rebuild = ss.nrebuild;
+    info->cg_iters_total = ss.iters_total;
+    info->cg_res0 = ss.res0;
     if (ss.status) return fail(info->status, status_text(ss.status));
     return CTBOP_OK;
 }

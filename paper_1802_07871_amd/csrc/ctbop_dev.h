@@ -67,7 +67,8 @@ struct SegState {
     double qshift;     // final re-projection of q onto sum q = Q
     double energy;
     unsigned long long nnz_long, nnz_short;   // list entries at the last build
-    double pad[2];
+    unsigned long long iters_total;           // charge-solve iterations since set-up
+    double res0;                              // starting residual of the last solve
 };
 
 // ---------------------------------------------------------------------------
@@ -121,6 +122,23 @@ struct Seg {
 struct Tile {
     int seg, row0;
 };
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8), each with its own L2.  Tiles are in spatial (cell) order, so the
+// tile of block b is chosen to give each XCD one contiguous run of tiles:
+// neighbouring tiles then share an L2 and their neighbour gathers hit it.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int q = nb / NXCD, r = nb % NXCD;
+    const int x = b % NXCD, k = b / NXCD;
+    return x * q + (x < r ? x : r) + k;
+}
+
+__device__ __forceinline__ Tile my_tile(const Tile *tiles)
+{
+    return tiles[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
+}
 
 // ---------------------------------------------------------------------------
 // helpers

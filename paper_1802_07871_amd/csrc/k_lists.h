@@ -33,7 +33,7 @@ __global__ void k_call_init(Seg *segs, int nseg, int force_rebuild)
 // since the last build (then no pair can have crossed into the cutoff).
 __global__ void k_check_disp(const Tile *tiles, Seg *segs)
 {
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     if (S.sst->rebuild) return;
     const int i = T.row0 + threadIdx.x;
@@ -70,7 +70,7 @@ __device__ __forceinline__ int cell_index(const Seg &S, const double s[3], int c
 // clear cell counters; mark padding rows
 __global__ void k_bin_clear(const Tile *tiles, Seg *segs)
 {
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     if (!S.sst->rebuild) return;
     const int tl = T.row0 / TILE;
@@ -92,7 +92,7 @@ __global__ void k_bin_clear(const Tile *tiles, Seg *segs)
 
 __global__ void k_bin(const Tile *tiles, Seg *segs)
 {
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     if (!S.sst->rebuild) return;
     const int i = T.row0 + threadIdx.x;
@@ -139,7 +139,7 @@ __global__ void k_scan(const int *seg_ids, Seg *segs)
 
 __global__ void k_scatter(const Tile *tiles, Seg *segs)
 {
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     if (!S.sst->rebuild) return;
     const int i = T.row0 + threadIdx.x;
@@ -155,7 +155,7 @@ __global__ void k_scatter(const Tile *tiles, Seg *segs)
 // the reference positions for the displacement test.
 __global__ void k_cell_sort(const Tile *tiles, Seg *segs)
 {
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     if (!S.sst->rebuild) return;
     const int tl = T.row0 / TILE;
@@ -194,7 +194,7 @@ template <typename R>
 __global__ void k_gather(const Tile *tiles, Seg *segs, int warm)
 {
     using V4 = typename Vec4<R>::type;
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     const int s = T.row0 + threadIdx.x;
     double q0 = 0.0;
@@ -230,7 +230,7 @@ __global__ void k_gather(const Tile *tiles, Seg *segs, int warm)
 // apply the projection of the starting charges onto sum q = Q
 __global__ void k_qfix(const Tile *tiles, Seg *segs)
 {
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     const int s = T.row0 + threadIdx.x;
     if (s < S.n) S.q[s] += S.sst->qshift;
@@ -267,7 +267,7 @@ template <typename R>
 __global__ void k_build(const Tile *tiles, Seg *segs, Params<R> P)
 {
     using V4 = typename Vec4<R>::type;
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     if (!S.sst->rebuild) return;
     __shared__ V4 dtab[NCODE];
@@ -330,7 +330,7 @@ __global__ void k_build(const Tile *tiles, Seg *segs, Params<R> P)
 // For every covalent entry (i -> j, d) the slot of (j -> i, -d) in row j.
 __global__ void k_rev(const Tile *tiles, Seg *segs)
 {
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     if (!S.sst->rebuild) return;
     const int s = T.row0 + threadIdx.x;

@@ -20,7 +20,7 @@ struct MdIO {
 
 __global__ void __launch_bounds__(TILE) k_md_kick_drift(const Tile *tiles, Seg *segs, MdIO io)
 {
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     const int i = T.row0 + threadIdx.x;
     if (i >= S.n) return;
@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(TILE) k_md_kick_drift(const Tile *tiles, Seg *
 // second half kick and the tile's kinetic energy
 __global__ void __launch_bounds__(TILE) k_md_kick(const Tile *tiles, Seg *segs, MdIO io)
 {
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     __shared__ double lds[4];
     const int i = T.row0 + threadIdx.x;

@@ -63,7 +63,7 @@ template <typename R, int LPR>
 __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs, Params<double> PD)
 {
     using V4 = typename Vec4<R>::type;
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     __shared__ V4 dtab[NCODE];
     __shared__ double lds[4 * 5];
@@ -129,6 +129,7 @@ __global__ void k_fin_assemble(const int *seg_ids, Seg *segs, CgCtl ctl)
         st->rho = tot[1] - w * tot[0];
         st->beta = 0.0;
         st->res = sqrt(fmax(res2, 0.0));
+        st->res0 = st->res;
         st->mshift = st->mu_prev - w;
         st->iters = 0;
         st->qshift = 0.0;
@@ -139,7 +140,7 @@ __global__ void k_fin_assemble(const int *seg_ids, Seg *segs, CgCtl ctl)
 // r <- r - w,  p <- D^-1 r + beta p
 __global__ void __launch_bounds__(TILE) k_cg_dir(const Tile *tiles, Seg *segs)
 {
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     if (S.sst->done) return;
     const int s = T.row0 + threadIdx.x;
@@ -150,15 +151,20 @@ __global__ void __launch_bounds__(TILE) k_cg_dir(const Tile *tiles, Seg *segs)
     S.p[s] = S.dinv[s] * r + beta * S.p[s];
 }
 
-// s = H p and the tile's share of p^T s
-template <typename R, int LPR>
+// s = H p and the tile's share of p^T s.  LPR lanes per row; lane l takes
+// entries l, l + LPR, ... so each load instruction reads consecutive entries
+// (and, rows being in cell order, mostly neighbouring p values); U entries
+// per lane per step keep U independent gathers in flight.  Entries past the
+// row's count are masked before their loads.
+template <typename R, int LPR, int U>
 __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
 {
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     if (S.sst->done) return;
     __shared__ double lds[4];
     const R *H = reinterpret_cast<const R *>(S.H);
+    const double *p = S.p;
     constexpr int G = TILE / LPR;
     const int lane = threadIdx.x % LPR;
     double pap = 0.0;
@@ -169,10 +175,19 @@ __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
         const uint32_t *row = S.lidx + (size_t)s * S.Wl;
         const R *hrow = H + (size_t)s * S.Wl;
         double acc = 0.0;
-        for (int e = lane; e < cnt; e += LPR) acc += (double)hrow[e] * S.p[row[e] & J_MASK];
+        for (int e = lane; e < cnt; e += U * LPR) {
+            double a[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int ee = e + u * LPR;
+                a[u] = (ee < cnt) ? (double)hrow[ee] * p[row[ee] & J_MASK] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) acc += a[u];
+        }
         acc = group_sum<LPR>(acc);
         if (lane == 0) {
-            const double ps = S.p[s];
+            const double ps = p[s];
             const double y = S.jd[s] * ps + acc;
             S.s[s] = y;
             pap += ps * y;
@@ -205,7 +220,7 @@ __global__ void k_fin_alpha(const int *seg_ids, Seg *segs)
 // q += alpha p, r -= alpha s, and the tile's sums for w, rho and the test
 __global__ void __launch_bounds__(TILE) k_cg_update(const Tile *tiles, Seg *segs)
 {
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     if (S.sst->done) return;
     __shared__ double lds[4 * 5];
@@ -246,6 +261,7 @@ __global__ void k_fin_update(const int *seg_ids, Seg *segs, CgCtl ctl)
         st->mshift -= w;
         st->res = sqrt(fmax(res2, 0.0));
         st->iters += 1;
+        st->iters_total += 1;
         st->qshift = (S.Q - tot[4]) / S.n;
         if (st->res < ctl.tol) st->done = 1;
         else if (st->iters >= ctl.maxit) { st->done = 1; st->status |= ST_NOCONV; }
@@ -258,7 +274,7 @@ template <typename R, int LPR>
 __global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *segs, Params<double> PD)
 {
     using V4 = typename Vec4<R>::type;
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     __shared__ V4 dtab[NCODE];
     __shared__ double lds[4];

@@ -150,7 +150,7 @@ template <typename R>
 __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Params<double> P)
 {
     using V4 = typename Vec4<R>::type;
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     __shared__ double4 dtab[NCODE];
     load_dtab2<double>(S, dtab);
@@ -225,7 +225,7 @@ template <typename R>
 __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs, Params<R> P)
 {
     using V4 = typename Vec4<R>::type;
-    const Tile T = tiles[blockIdx.x];
+    const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     __shared__ V4 dtab[NCODE];
     load_dtab2<R>(S, dtab);
