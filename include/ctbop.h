@@ -187,6 +187,65 @@ int ctbop_debug_lists(ctbop_ctx *ctx, int n, void *sys_dev, size_t sys_bytes, in
                       int short_cap, int *counts_long, int *j_long, double *d_long,
                       int *counts_short, int *j_short, double *d_short, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of independent evaluation requests            */
+/* ------------------------------------------------------------------------ */
+/* A server runs a scheduler thread on one stream over a caller-owned device
+ * arena.  Every admitted request becomes a segment (its own region of the
+ * arena with its inputs, outputs, lists and charges); each tick launches the
+ * set-up kernels for new segments and a few charge-solve iterations plus the
+ * gated force kernels for all active segments, each kernel once over all of
+ * them.  Requests are admitted in arrival order at tick boundaries while
+ * slots and arena bytes allow (HBM-budget admission); a request that does
+ * not fit waits.  A request with system_id >= 0 leaves its region (lists and
+ * charges) on the device after it finishes; the next request with that id
+ * and the same geometry reuses it (lists rebuilt only if atoms moved more
+ * than skin/2, charges warm-started); retained regions are evicted least
+ * recently used first when space runs out.  Each result is bitwise the one
+ * the request gets when it runs alone. */
+typedef struct ctbop_server ctbop_server;
+
+typedef struct {
+    int            n;             /* atoms                                              */
+    const double  *pos_host;      /* 3n doubles, SoA; copied at submit                 */
+    const int32_t *types_host;    /* n; copied at submit                                */
+    double         box[9];        /* as for compute                                     */
+    int            pbc[3];
+    double         total_charge;
+    long           system_id;     /* >= 0: keep lists and charges for the next request */
+    double        *E_host;        /* outputs (host, may be NULL): must stay valid until */
+    double        *F_host;        /* the result is polled; F is 3n SoA, q is n          */
+    double        *q_host;
+} ctbop_request;
+
+typedef struct {
+    long   ticket;
+    int    status;                /* CTBOP_* code of this request                       */
+    int    cg_iters;
+    int    n_atoms;
+    double t_submit, t_admit, t_done;   /* steady-clock seconds                         */
+} ctbop_result;
+
+/* Bytes of the server's own tables at the head of the arena. */
+size_t ctbop_server_table_bytes(int max_slots, int max_tiles);
+/* Arena bytes one request of n atoms in this cell occupies while it runs. */
+int ctbop_server_request_bytes(ctbop_ctx *ctx, int n, const double *box_host, const int *pbc_host, size_t *bytes);
+/* Start a server: arena_dev/arena_bytes caller-owned device memory, at most
+ * max_slots requests in flight, cg_per_tick solver iterations per tick (0: 8),
+ * all work on `stream` (its device is the current device). */
+int ctbop_server_create(ctbop_ctx *ctx, void *arena_dev, size_t arena_bytes, int max_slots, int cg_per_tick,
+                        void *stream, ctbop_server **srv);
+/* Queue a request (inputs copied); E_BUSY if the queue is full, E_NOMEM if it
+ * can never fit the arena. */
+int ctbop_server_submit(ctbop_server *srv, const ctbop_request *req, long *ticket);
+/* Take up to max finished results (waiting up to wait_s seconds for one). */
+int ctbop_server_poll(ctbop_server *srv, ctbop_result *out, int max, double wait_s, int *n_done);
+/* ticks, admitted, completed, pending, active, retained, arena bytes in use,
+ * peak bytes, busy seconds (first nout of these). */
+int ctbop_server_stats(ctbop_server *srv, double *out, int nout);
+/* Stop the scheduler (pending requests are dropped) and release host state. */
+int ctbop_server_destroy(ctbop_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -393,7 +393,7 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
     int warm = 0;
     if ((flags & CTBOP_FLAG_WARM_START) && !P.fresh) warm = (flags & CTBOP_FLAG_EXTRAPOLATE) ? 2 : 1;
     const int *sid = P.dsegid;
-    hipLaunchKernelGGL(k_call_init, g1, dim3(64), 0, st, P.dseg, 1, force);
+    hipLaunchKernelGGL(k_call_init, g1, dim3(64), 0, st, sid, P.dseg, 1, force);
     hipLaunchKernelGGL(k_check_disp, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_bin_clear, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_bin, g, b, 0, st, P.dtiles, P.dseg);
@@ -408,7 +408,7 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
         hipLaunchKernelGGL(k_build<R>, g, b, 0, st, P.dtiles, P.dseg, prm);
     }
     hipLaunchKernelGGL(k_rev, g, b, 0, st, P.dtiles, P.dseg);
-    hipLaunchKernelGGL(k_mark_built, g1, dim3(64), 0, st, P.dseg, 1);
+    hipLaunchKernelGGL(k_mark_built, g1, dim3(64), 0, st, sid, P.dseg, 1);
     {
         Timed t(ctx, 3, st);
         hipLaunchKernelGGL((k_bond<R>), g, b, 0, st, P.dtiles, P.dseg, ctx->pd);
@@ -452,13 +452,13 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
     if (iters_out) *iters_out = ctx->host_flag[1];
     {
         Timed t(ctx, 4, st);
-        hipLaunchKernelGGL((k_force_cov<R>), g, b, 0, st, P.dtiles, P.dseg, prm);
+        hipLaunchKernelGGL((k_force_cov<R>), g, b, 0, st, P.dtiles, P.dseg, prm, 0);
     }
     {
         Timed t(ctx, 1, st);
-        hipLaunchKernelGGL((k_force_coul<R, LPR>), g, b, 0, st, P.dtiles, P.dseg, ctx->pd);
+        hipLaunchKernelGGL((k_force_coul<R, LPR>), g, b, 0, st, P.dtiles, P.dseg, ctx->pd, 0);
     }
-    hipLaunchKernelGGL(k_fin_energy, g1, b, 0, st, sid, P.dseg);
+    hipLaunchKernelGGL(k_fin_energy, g1, b, 0, st, sid, P.dseg, 0);
     HIPCHK(hipGetLastError());
     return CTBOP_OK;
 }
@@ -738,3 +738,5 @@ int ctbop_debug_lists(ctbop_ctx *ctx, int n, void *sys, size_t sys_bytes, int lo
 }
 
 } // extern "C"
+
+#include "server.h"

@@ -58,6 +58,8 @@ struct SegState {
     int maxl, maxs;    // largest list rows at the last build
     int built;         // lists exist
     int nhist;         // charge solutions kept for the starting-charge predictor (0..3)
+    int warm;          // per-segment start mode when a launch passes warm < 0 (serving)
+    int forces_done;   // serving: forces and energy of the current request are written
     int nrebuild;      // rebuilds since the system buffer was set up
     double w;          // current residual shift
     double rho, alpha, beta, res;

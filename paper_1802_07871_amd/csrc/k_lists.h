@@ -17,16 +17,19 @@ namespace ctbop {
 
 __global__ void k_set_seg(Seg *dst, Seg src) { *dst = src; }
 
-__global__ void k_call_init(Seg *segs, int nseg, int force_rebuild)
+__global__ void k_set_warm(SegState *st, int warm) { st->warm = warm; }
+
+__global__ void k_call_init(const int *seg_ids, Seg *segs, int nseg, int force_rebuild)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nseg) return;
-    SegState *st = segs[k].sst;
+    SegState *st = segs[seg_ids[k]].sst;
     st->rebuild = (force_rebuild || !st->built) ? 1 : 0;
     st->ticket = 0;
     st->done = 0;
     st->iters = 0;
     st->status = 0;
+    st->forces_done = 0;
 }
 
 // A neighbour list rebuild is needed once any atom moved more than skin/2
@@ -212,8 +215,9 @@ __global__ void k_gather(const Tile *tiles, Seg *segs, int warm)
         v.w = (R)w.w;
         reinterpret_cast<V4 *>(S.xs)[s] = v;
         if ((void *)S.xs64 != S.xs) S.xs64[s] = w;
-        if (warm) {
-            const int nh = warm == 2 ? S.sst->nhist : 1;
+        const int wm = warm < 0 ? S.sst->warm : warm;
+        if (wm) {
+            const int nh = wm == 2 ? S.sst->nhist : 1;
             if (nh >= 3) q0 = 3.0 * S.q_state[i] - 3.0 * S.q_h1[i] + S.q_h2[i];
             else if (nh == 2) q0 = 2.0 * S.q_state[i] - S.q_h1[i];
             else if (nh == 1) q0 = S.q_state[i];
@@ -351,12 +355,14 @@ __global__ void k_rev(const Tile *tiles, Seg *segs)
     if (bad) atomicOr(&S.sst->status, ST_REV);
 }
 
-__global__ void k_mark_built(Seg *segs, int nseg)
+__global__ void k_mark_built(const int *seg_ids, Seg *segs, int nseg)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < nseg && segs[k].sst->rebuild) {
-        segs[k].sst->built = 1;
-        segs[k].sst->nrebuild += 1;
+    if (k >= nseg) return;
+    SegState *st = segs[seg_ids[k]].sst;
+    if (st->rebuild) {
+        st->built = 1;
+        st->nrebuild += 1;
     }
 }
 

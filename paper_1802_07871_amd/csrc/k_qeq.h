@@ -271,11 +271,12 @@ __global__ void k_fin_update(const int *seg_ids, Seg *segs, CgCtl ctl)
 // Coulomb forces and energy at the equilibrated charges, plus the covalent
 // forces and energies: writes F, q (user order) and the tile's energy.
 template <typename R, int LPR>
-__global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *segs, Params<double> PD)
+__global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *segs, Params<double> PD, int gate)
 {
     using V4 = typename Vec4<R>::type;
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
+    if (gate && (!S.sst->done || S.sst->forces_done)) return;
     __shared__ V4 dtab[NCODE];
     __shared__ double lds[4];
     load_dtab2<R>(S, dtab);
@@ -334,9 +335,10 @@ __global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *seg
     tile_partials<1>(S, T.row0 / TILE, v, lds);
 }
 
-__global__ void k_fin_energy(const int *seg_ids, Seg *segs)
+__global__ void k_fin_energy(const int *seg_ids, Seg *segs, int gate)
 {
     const Seg &S = segs[seg_ids[blockIdx.x]];
+    if (gate && (!S.sst->done || S.sst->forces_done)) return;
     __shared__ double lds[4];
     double tot[1];
     seg_total<1>(S, lds, tot);
@@ -346,7 +348,17 @@ __global__ void k_fin_energy(const int *seg_ids, Seg *segs)
         if (S.E_out) *S.E_out = tot[0];
         st->mu_prev = st->mshift;
         st->nhist = st->nhist < 3 ? st->nhist + 1 : 3;
+        st->forces_done = 1;
     }
+}
+
+// serving: per-segment flags (done, forces_done, status, iterations)
+__global__ void k_collect(const int *seg_ids, Seg *segs, int nseg, int4 *out)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nseg) return;
+    const SegState *st = segs[seg_ids[k]].sst;
+    out[k] = make_int4(st->done, st->forces_done, st->status, st->iters);
 }
 
 } // namespace ctbop

@@ -222,11 +222,13 @@ __device__ __forceinline__ R pair_dvdr(const Params<R> &P, int pp, R r, R b)
 }
 
 template <typename R>
-__global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs, Params<R> P)
+__global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs, Params<R> P, int gate)
 {
     using V4 = typename Vec4<R>::type;
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
+    // serving: only segments whose charge solve finished and whose forces are pending
+    if (gate && (!S.sst->done || S.sst->forces_done)) return;
     __shared__ V4 dtab[NCODE];
     load_dtab2<R>(S, dtab);
     const int m = T.row0 + threadIdx.x;
