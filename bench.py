@@ -61,6 +61,145 @@ def workload(args):
     return s
 
 
+def _make_request(req):
+    from ctbop_inputs import generators as G
+    s = G.request_structure(req)
+    return s.pos, s.types, s.box, s.pbc
+
+
+def make_requests(count: int, seed: int = 1002, workers: int = 16):
+    """Seeded serving requests (N log-uniform 8..20000, C fraction U[0.5,1],
+    2.0-3.2 g/cm^3, half clusters / half periodic cells), generated in a fork
+    pool before the GPU is touched."""
+    import multiprocessing as mp
+    from ctbop_inputs import generators as G
+    reqs = G.serving_requests(count, seed=seed)
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_make_request, reqs, chunksize=8)
+
+
+def _pct(v, p):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), p)) if len(v) else None
+
+
+def serving_bench(pot_factory, reqs, qps_fracs=(0.9,), baseline_count=None, arena_gb=24, max_slots=512,
+                  cg_per_tick=8):
+    """Continuous-batching server vs per-request plain launches on the same
+    GPU and the same requests (same charge-solve tolerance)."""
+    import numpy as np
+    import torch
+    from paper_1802_07871_amd.serving import Server
+    natoms = np.array([len(r[1]) for r in reqs])
+    out = {"requests": len(reqs), "atoms_total": int(natoms.sum()), "atoms_mean": float(natoms.mean())}
+    srv = Server(pot_factory(), int(arena_gb) << 30, max_slots=max_slots, cg_per_tick=cg_per_tick)
+    # warm-up: a few requests through the server
+    srv.wait_all([srv.submit(*reqs[k]) for k in range(min(8, len(reqs)))])
+    # saturation: everything submitted at once
+    t0 = time.perf_counter()
+    tickets = [srv.submit(*r) for r in reqs]
+    got = srv.wait_all(tickets, timeout=600)
+    t_sat = time.perf_counter() - t0
+    bad = sum(1 for g in got.values() if g["status"] != 0)
+    rate = len(reqs) / t_sat
+    out["saturation"] = {"requests_per_s": rate, "atoms_per_s": float(natoms.sum()) / t_sat, "seconds": t_sat,
+                         "failed": bad}
+    # open-loop Poisson arrivals
+    levels = []
+    rng = np.random.Generator(np.random.PCG64(1005))
+    for f in qps_fracs:
+        qps = f * rate
+        arr = np.cumsum(rng.exponential(1.0 / qps, size=len(reqs)))
+        lat = []
+        tick = {}
+        t0 = time.perf_counter()
+        k = 0
+        pending = set()
+        while k < len(reqs) or pending:
+            now = time.perf_counter() - t0
+            while k < len(reqs) and arr[k] <= now:
+                t = srv.submit(*reqs[k])
+                tick[t] = t0 + arr[k]
+                pending.add(t)
+                k += 1
+            wait = 0.0 if k >= len(reqs) else max(0.0, min(0.002, arr[k] - now))
+            for r in srv.poll(wait=wait if wait > 0 else 0.001):
+                pending.discard(r["ticket"])
+                # from the scheduled arrival (both clocks are CLOCK_MONOTONIC)
+                lat.append(r["t_done"] - tick[r["ticket"]])
+        dur = time.perf_counter() - t0
+        levels.append({"qps_frac": f, "qps": qps, "p50_ms": _pct(lat, 50) * 1e3, "p99_ms": _pct(lat, 99) * 1e3,
+                       "throughput_req_s": len(reqs) / dur, "atoms_per_s": float(natoms.sum()) / dur})
+    out["batched"] = levels
+    st = srv.stats()
+    out["server"] = {k: st[k] for k in ("ticks", "peak_bytes")}
+    srv.close()
+    del srv
+    torch.cuda.synchronize()
+    # per-request plain launches: service time of each request alone (fresh
+    # system buffer, one call), then the FIFO single-stream queue under the
+    # same arrivals
+    pot = pot_factory()
+    nb = len(reqs) if baseline_count is None else min(baseline_count, len(reqs))
+    svc = []
+    import paper_1802_07871_amd as ct
+    for k in range(nb):
+        pos, types, box, pbc = reqs[k]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pot.compute(pos, types, box, pbc, warm=False, sysbuf=ct.System(pot, len(types), box, pbc))
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t0)
+    svc = np.array(svc)
+    base_rate = nb / svc.sum()
+    out["unbatched"] = {"requests_per_s": float(base_rate), "atoms_per_s": float(natoms[:nb].sum() / svc.sum()),
+                        "requests_timed": nb}
+    blev = []
+    rng = np.random.Generator(np.random.PCG64(1005))
+    for f in qps_fracs:
+        qps = f * rate
+        arr = np.cumsum(rng.exponential(1.0 / qps, size=len(reqs)))[:nb]
+        done = np.zeros(nb)
+        prev = 0.0
+        for k in range(nb):
+            prev = max(arr[k], prev) + svc[k]
+            done[k] = prev
+        lat = done - arr
+        blev.append({"qps_frac": f, "qps": qps, "p50_ms": _pct(lat, 50) * 1e3, "p99_ms": _pct(lat, 99) * 1e3})
+    out["unbatched"]["levels"] = blev
+    out["speedup_throughput"] = out["saturation"]["requests_per_s"] / base_rate
+    # equal load below the unbatched capacity: both forms at 0.5x the unbatched rate
+    qps = 0.5 * base_rate
+    nlow = min(len(reqs), max(64, int(qps * 4.0)))
+    rng = np.random.Generator(np.random.PCG64(1006))
+    arr = np.cumsum(rng.exponential(1.0 / qps, size=nlow))
+    done = np.zeros(nlow)
+    prev = 0.0
+    for k in range(nlow):
+        prev = max(arr[k], prev) + svc[k % nb]
+        done[k] = prev
+    ulat = done - arr
+    srv = Server(pot_factory(), int(arena_gb) << 30, max_slots=max_slots, cg_per_tick=cg_per_tick)
+    srv.wait_all([srv.submit(*reqs[k]) for k in range(min(8, len(reqs)))])
+    lat, tick, pending, k = [], {}, set(), 0
+    t0 = time.perf_counter()
+    while k < nlow or pending:
+        now = time.perf_counter() - t0
+        while k < nlow and arr[k] <= now:
+            t = srv.submit(*reqs[k])
+            tick[t] = t0 + arr[k]
+            pending.add(t)
+            k += 1
+        for r in srv.poll(wait=0.001):
+            pending.discard(r["ticket"])
+            lat.append(r["t_done"] - tick[r["ticket"]])
+    srv.close()
+    out["equal_load"] = {"qps": qps, "requests": nlow,
+                         "batched_p50_ms": _pct(lat, 50) * 1e3, "batched_p99_ms": _pct(lat, 99) * 1e3,
+                         "unbatched_p50_ms": _pct(ulat, 50) * 1e3, "unbatched_p99_ms": _pct(ulat, 99) * 1e3}
+    return out
+
+
 def cpu_baseline(theta, nx: int, nsteps: int):
     """The CPU oracle (FP64, OpenMP) on a bounded sample of the same workload:
     the same stepped, depleted slab at nx x nx cells, nsteps MD steps."""
@@ -91,6 +230,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-nx", type=int, default=40)
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--serving", action="store_true",
+                    help="serving benchmark only: 4096 Poisson requests at 5 loads vs per-request launches")
+    ap.add_argument("--serve-requests", type=int, default=None)
+    ap.add_argument("--no-serving", action="store_true", help="skip the compact serving measurement")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (scales HBM byte counters)")
     args = ap.parse_args()
@@ -99,6 +242,15 @@ def main():
               "decomposition); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    # serving requests are generated before the GPU is touched
+    reqs = None
+    if args.serving or not args.no_serving:
+        nreq = args.serve_requests or (4096 if args.serving else 512)
+        t0 = time.perf_counter()
+        reqs = make_requests(nreq)
+        print(f"bench: {nreq} serving requests generated in {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+
     import numpy as np
     import torch
 
@@ -106,6 +258,18 @@ def main():
     from ctbop_inputs import params as PR
 
     torch.cuda.set_device(0)
+    if args.serving:
+        theta = PR.load()
+        res = serving_bench(lambda: ct.Potential(theta), reqs, qps_fracs=(0.25, 0.5, 0.75, 0.9, 1.1))
+        line = {"metric": "batched-request p50/p99 latency (continuous batching vs per-request launches)",
+                "value": res["batched"][3]["p99_ms"], "unit": "ms (p99 at 0.9x saturation)",
+                "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f32-terms/f64-sums",
+                "config": {"workload": f"{res['requests']} requests, N log-uniform 8..20000 "
+                                       f"(mean {res['atoms_mean']:.0f}), random Si/C clusters and cells, "
+                                       "Poisson arrivals, charges to 1e-9"},
+                "serving": res}
+        print(json.dumps(line))
+        return
     if args.calibrate_copy_mb > 0:
         nb = args.calibrate_copy_mb << 20
         src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
@@ -203,6 +367,12 @@ def main():
         "kernels": kernels,
         "energy_change_eV_per_atom": float((thermo[1].sum() - thermo[0].sum()) / n),
     }
+    if reqs is not None:
+        print("bench: compact serving measurement", file=sys.stderr, flush=True)
+        del sysb
+        torch.cuda.empty_cache()
+        out["serving"] = serving_bench(lambda: ct.Potential(theta), reqs, qps_fracs=(0.9,), baseline_count=128,
+                                       arena_gb=16)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(theta, args.cpu_nx, args.cpu_steps)

@@ -418,6 +418,8 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
         Timed t(ctx, 2, st);
         hipLaunchKernelGGL((k_assemble<R, LPR>), g, b, 0, st, P.dtiles, P.dseg, ctx->pd);
     }
+    hipLaunchKernelGGL(k_fin_w0, g1, b, 0, st, sid, P.dseg);
+    hipLaunchKernelGGL(k_shift_stats, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_fin_assemble, g1, b, 0, st, sid, P.dseg, ctl);
     HIPCHK(hipGetLastError());
     // charge solve: launch iterations in batches, then read the convergence flag

@@ -105,16 +105,14 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
             S.r[s] = r;
             S.p[s] = 0.0;
             acc5[0] += r * di;
-            acc5[1] += r * r * di;
-            acc5[2] += r;
-            acc5[3] += r * r;
             acc5[4] += di;
         }
     }
     tile_partials<5>(S, T.row0 / TILE, acc5, lds);
 }
 
-__global__ void k_fin_assemble(const int *seg_ids, Seg *segs, CgCtl ctl)
+// First pass over the starting residual: its D-weighted mean w0.
+__global__ void k_fin_w0(const int *seg_ids, Seg *segs)
 {
     const Seg &S = segs[seg_ids[blockIdx.x]];
     __shared__ double lds[4 * 5];
@@ -122,15 +120,51 @@ __global__ void k_fin_assemble(const int *seg_ids, Seg *segs, CgCtl ctl)
     seg_total<5>(S, lds, tot);
     if (threadIdx.x == 0) {
         SegState *st = S.sst;
-        const double w = tot[0] / tot[4];
-        const double res2 = (tot[3] - tot[2] * tot[2] / S.n) / S.n;
         st->sdinv = tot[4];
+        st->w = tot[0] / tot[4];
+    }
+}
+
+// Second pass: r <- r - w0 and the sums of the shifted residual.  Forming
+// r^T z and the projected norm from one-pass sums of the unshifted residual
+// cancels catastrophically when r is nearly constant (for instance a
+// single-species input, whose exact residual is constant).
+__global__ void __launch_bounds__(TILE) k_shift_stats(const Tile *tiles, Seg *segs)
+{
+    const Tile T = my_tile(tiles);
+    const Seg &S = segs[T.seg];
+    __shared__ double lds[4 * 4];
+    const int s = T.row0 + threadIdx.x;
+    double v[4] = {0, 0, 0, 0};
+    if (s < S.n) {
+        const double r = S.r[s] - S.sst->w;
+        const double di = S.dinv[s];
+        S.r[s] = r;
+        v[0] = r * di;
+        v[1] = r * r * di;
+        v[2] = r;
+        v[3] = r * r;
+    }
+    tile_partials<4>(S, T.row0 / TILE, v, lds);
+}
+
+__global__ void k_fin_assemble(const int *seg_ids, Seg *segs, CgCtl ctl)
+{
+    const Seg &S = segs[seg_ids[blockIdx.x]];
+    __shared__ double lds[4 * 4];
+    double tot[4];
+    seg_total<4>(S, lds, tot);
+    if (threadIdx.x == 0) {
+        SegState *st = S.sst;
+        const double w0 = st->w;
+        const double w = tot[0] / st->sdinv;          // residual shift left after the first pass
+        const double res2 = (tot[3] - tot[2] * tot[2] / S.n) / S.n;
         st->w = w;
         st->rho = tot[1] - w * tot[0];
         st->beta = 0.0;
         st->res = sqrt(fmax(res2, 0.0));
         st->res0 = st->res;
-        st->mshift = st->mu_prev - w;
+        st->mshift = st->mu_prev - w0 - w;
         st->iters = 0;
         st->qshift = 0.0;
         st->done = (st->res < ctl.tol) ? 1 : 0;

@@ -298,6 +298,8 @@ int server_tick(ctbop_server *S, const Params<R> &prm)
         hipLaunchKernelGGL((k_bond<R>), g, b, 0, st, T, S->dsegs, ctx->pd);
         hipLaunchKernelGGL((k_assemble<R, LPR>), g, b, 0, st, T, S->dsegs, ctx->pd);
         CgCtl ctl{ctx->opts.cg_tol, ctx->opts.cg_maxit};
+        hipLaunchKernelGGL(k_fin_w0, gs, b, 0, st, sid, S->dsegs);
+        hipLaunchKernelGGL(k_shift_stats, g, b, 0, st, T, S->dsegs);
         hipLaunchKernelGGL(k_fin_assemble, gs, b, 0, st, sid, S->dsegs, ctl);
     }
     {

@@ -155,3 +155,20 @@ def test_error_codes(ct, theta):
     with pytest.raises(ct.CtbopError) as e:
         ct.Potential(bad).compute(s2.pos, s2.types, s2.box, s2.pbc)
     assert e.value.code in (ct.E_QEQ_NOT_PD, ct.E_QEQ_NOCONV)
+
+
+def test_single_species_inputs_regression(ct, orc, theta):
+    """All-carbon inputs have a constant starting residual; its statistics must
+    be formed after shifting by the mean (one-pass sums once cancelled to
+    rounding noise and reported a spurious non-positive-definite solve)."""
+    cases = [G.random_system(8, 1.0, 3.2, True, seed=81), G.random_system(600, 1.0, 2.6, False, seed=82),
+             G.random_system(1200, 1.0, 3.1, True, seed=83)]
+    for s in cases:
+        print(f"[single species] n={s.n}", flush=True)
+        pot = ct.Potential(theta)
+        E, F, q, info = pot.compute(s.pos, s.types, s.box, s.pbc, warm=False)
+        assert info["status"] == 0
+        Eo, Fo, qo, _ = orc.evaluate(s.pos, s.types, s.box, s.pbc, theta, tol=1e-13)
+        assert np.abs(q.cpu().numpy() - qo).max() < 1e-12
+        assert abs(E - Eo) / s.n < 1e-6
+        assert np.linalg.norm(F.cpu().numpy() - Fo) / np.linalg.norm(Fo) < 1e-5
