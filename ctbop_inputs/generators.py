@@ -261,7 +261,8 @@ def graphene(nx: int, ny: int, n_sw: int, seed: int, vacuum: float = 15.0,
              a_cc: float = 1.42, sigma: float = 0.03) -> Structure:
     """Graphene sheet, rectangular cell of nx x ny four-atom cells, periodic in
     plane with `vacuum` along z, and `n_sw` Stone-Wales defects (a C-C bond
-    turned by 90 degrees about its midpoint) at well-separated bonds."""
+    turned by 90 degrees about its midpoint) at bonds at least 8 Angstrom
+    apart: as many as fit, up to n_sw (meta["n_sw"] holds the number placed)."""
     a = a_cc * np.sqrt(3.0)
     basis = np.array([[0, 0], [0, a_cc], [a / 2, np.sqrt(3) * a / 2],
                       [a / 2, np.sqrt(3) * a / 2 + a_cc]])
@@ -277,6 +278,7 @@ def graphene(nx: int, ny: int, n_sw: int, seed: int, vacuum: float = 15.0,
     used = np.zeros(len(pos), dtype=bool)
     centres = []
     for _ in range(n_sw):
+        placed = False
         for _try in range(1000):
             c = int(rng.integers(ncell))
             i, j = (4 * c, 4 * c + 1) if rng.uniform() < 0.5 else (4 * c + 2, 4 * c + 3)
@@ -288,9 +290,10 @@ def graphene(nx: int, ny: int, n_sw: int, seed: int, vacuum: float = 15.0,
                 if np.hypot(*dd) < 8.0:
                     far = False
             if far and not used[i] and not used[j]:
+                placed = True
                 break
-        else:
-            raise RuntimeError("could not place Stone-Wales defect")
+        if not placed:
+            break
         used[i] = used[j] = True
         centres.append(mid)
         for k in (i, j):
@@ -300,7 +303,7 @@ def graphene(nx: int, ny: int, n_sw: int, seed: int, vacuum: float = 15.0,
     pos[:, 0] %= lx
     pos[:, 1] %= ly
     return Structure(pos, np.full(len(pos), C, dtype=np.int32), np.diag([lx, ly, lz]),
-                     np.array([True, True, False]), meta={"kind": "graphene", "n_sw": n_sw})
+                     np.array([True, True, False]), meta={"kind": "graphene", "n_sw": len(centres)})
 
 
 def fit_batch(count: int = 256, seed: int = 1003, nmin: int = 64, nmax: int = 2000):

@@ -129,6 +129,12 @@ void ctbop_default_opts(ctbop_opts *o);
 int ctbop_create(const double *params_host, int n_params, const ctbop_opts *opts, ctbop_ctx **ctx);
 int ctbop_destroy(ctbop_ctx *ctx);
 
+/* Replace the context's parameters (host, copied; the same checks as
+ * ctbop_create).  The list radii may change with them, so every system
+ * buffer used with this context starts over at its next call (lists rebuilt,
+ * cold charge start).  E_BUSY while a server runs on this context. */
+int ctbop_set_params(ctbop_ctx *ctx, const double *params_host, int n_params);
+
 /* Bytes of the per-system device buffer for n atoms in this cell.  The buffer
  * is reused across calls for the same system (it keeps the lists, the sort
  * order and the charges for the warm start); its content is opaque. */
@@ -161,6 +167,32 @@ int ctbop_md_run(ctbop_ctx *ctx, int n, double *x_dev, double *v_dev, const int3
                  double total_charge, double dt_fs, int nsteps, int thermo_every,
                  void *sys_dev, size_t sys_bytes, double *F_dev, double *q_dev,
                  double *thermo_host, ctbop_info *info, void *stream);
+
+/* Gradient of a loss L(E, F, q) with respect to the 56 parameters, at the
+ * configuration and equilibrated charges of the last evaluation on `sys_dev`
+ * (which must have used the current parameters; E_INVAL otherwise), for
+ * force/energy/charge fits (Methods: the parameters are fitted to energies,
+ * forces and charges).  The caller gives the seeds
+ *   dL_dE       dL/dE (host scalar)
+ *   dL_dF_dev   double[3n] SoA dL/dF (device)
+ *   dL_dq_dev   double[n] dL/dq (device) or NULL for zero
+ * and receives grad_host[56] = dL/dtheta (host).  With the charges defined
+ * by  H q + chi = mu 1, sum q = Q,  the result is
+ *   w dE/dtheta + d(v.F)/dtheta  at fixed q   (w = dL/dE, v = dL/dF)
+ *   - lambda . (dH/dtheta q + dchi/dtheta),   P H P lambda = P a, sum lambda = 0,
+ *   a = dL/dq + d(v.F)/dq,
+ * where P projects onto sum = 0: one adjoint charge solve (the forward's
+ * projected PCG, stopped at a projected residual of cg_tol times its start)
+ * and forward-mode (dual-number) passes of the covalent and Coulomb kernels
+ * per parameter.  Masses get 0.  adj_ws_dev: caller device scratch of at least
+ * ctbop_param_grad_bytes() bytes.  The system buffer's forward state
+ * (charges, lists, warm start) is left as it was.  cg_iters (host, may be
+ * NULL) gets the adjoint solve's iterations.  Waits for the stream. */
+int ctbop_param_grad_bytes(ctbop_ctx *ctx, int n, const double *box_host, const int *pbc_host, size_t *bytes);
+int ctbop_param_grad(ctbop_ctx *ctx, int n, const double *box_host, const int *pbc_host, void *sys_dev,
+                     size_t sys_bytes, void *adj_ws_dev, size_t adj_bytes, double dL_dE,
+                     const double *dL_dF_dev, const double *dL_dq_dev, double *grad_host, int *cg_iters,
+                     void *stream);
 
 /* Device status word of `sys` (waits for the stream). */
 int ctbop_status(ctbop_ctx *ctx, void *sys_dev, size_t sys_bytes, void *stream, int *code);

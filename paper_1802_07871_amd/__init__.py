@@ -53,7 +53,7 @@ class Info(ctypes.Structure):
 _lib = None
 EXPORTS = ("ctbop_default_opts", "ctbop_create", "ctbop_destroy", "ctbop_system_bytes",
            "ctbop_compute_energy_forces_charges", "ctbop_md_run", "ctbop_status", "ctbop_last_error",
-           "ctbop_debug_lists", "ctbop_profile")
+           "ctbop_debug_lists", "ctbop_profile", "ctbop_set_params", "ctbop_param_grad_bytes", "ctbop_param_grad")
 
 
 def lib():
@@ -76,6 +76,9 @@ def lib():
         L.ctbop_last_error.restype = ctypes.c_char_p
         L.ctbop_debug_lists.argtypes = [vp, i32, vp, sz, i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.ctbop_profile.argtypes = [vp, i32, i32, vp, vp, vp, i32]
+        L.ctbop_set_params.argtypes = [vp, vp, i32]
+        L.ctbop_param_grad_bytes.argtypes = [vp, i32, vp, vp, ctypes.POINTER(sz)]
+        L.ctbop_param_grad.argtypes = [vp, i32, vp, vp, vp, sz, vp, sz, dbl, vp, vp, vp, ctypes.POINTER(i32), vp]
         _lib = L
     return _lib
 
@@ -146,6 +149,39 @@ class Potential:
 
     def system(self, n, box, pbc) -> System:
         return System(self, n, box, pbc)
+
+    def set_params(self, params):
+        """Replace the parameters in place (every system buffer starts over)."""
+        th = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+        if th.shape != (N_PARAMS,):
+            raise ValueError("expected 56 parameters")
+        _check(lib().ctbop_set_params(self.ctx, th.ctypes.data, N_PARAMS))
+        self.params = th
+
+    def param_grad(self, sysbuf: System, box, pbc, dL_dE, dL_dF_soa, dL_dq=None, ws=None):
+        """dL/dtheta (numpy [56]) at the last evaluation on `sysbuf`, for the
+        seeds dL/dE (float), dL/dF (3n SoA float64 CUDA tensor) and dL/dq (n
+        float64 CUDA tensor or None).  Returns (grad, adjoint CG iterations)."""
+        torch = _torch()
+        n = sysbuf.n
+        b, p = _box_pbc(box, pbc)
+        assert dL_dF_soa.dtype == torch.float64 and dL_dF_soa.is_cuda and dL_dF_soa.numel() == 3 * n
+        dL_dF_soa = dL_dF_soa.contiguous()
+        if dL_dq is not None:
+            assert dL_dq.dtype == torch.float64 and dL_dq.is_cuda and dL_dq.numel() == n
+            dL_dq = dL_dq.contiguous()
+        nb = ctypes.c_size_t()
+        _check(lib().ctbop_param_grad_bytes(self.ctx, int(n), b.ctypes.data, p.ctypes.data, ctypes.byref(nb)))
+        if ws is None or ws.numel() < nb.value:
+            ws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+        g = np.zeros(N_PARAMS)
+        it = ctypes.c_int()
+        _check(lib().ctbop_param_grad(self.ctx, int(n), b.ctypes.data, p.ctypes.data, sysbuf.ptr(), sysbuf.nbytes,
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), float(dL_dE),
+                                      ctypes.c_void_p(dL_dF_soa.data_ptr()),
+                                      ctypes.c_void_p(dL_dq.data_ptr()) if dL_dq is not None else None,
+                                      g.ctypes.data, ctypes.byref(it), _stream()))
+        return g, int(it.value)
 
     def _sys_for(self, n, box, pbc, sysbuf):
         if sysbuf is not None:

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -71,6 +72,11 @@ struct ctbop_ctx {
     Params<double> pd;
     std::unordered_map<void *, Sig> seen;
     std::unordered_map<void *, int> last_iters;
+    // parameter set generation, and the generation each system buffer was
+    // last evaluated with (the adjoint needs the evaluation it differentiates)
+    unsigned long param_gen = 0;
+    std::unordered_map<void *, unsigned long> eval_gen;
+    std::atomic<int> servers{0};  // live servers on this context
     int *host_flag = nullptr;    // pinned: done, iters
     // optional per-kernel timing with HIP events on the caller's stream
     int profile = 0;
@@ -467,8 +473,23 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
 
 int eval_any(ctbop_ctx *ctx, Prep &P, int flags, int *iters)
 {
+    ctx->eval_gen[P.base] = ctx->param_gen;
     if (ctx->opts.fp64) return launch_eval<double>(ctx, P, ctx->pd, flags, iters);
     return launch_eval<float>(ctx, P, ctx->pf, flags, iters);
+}
+
+int check_params(const double *params, int n_params)
+{
+    if (!params) return fail(CTBOP_E_INVAL, "null argument");
+    if (n_params != CTBOP_N_PARAMS) return fail(CTBOP_E_INVAL, "expected 56 parameters");
+    for (int t = 0; t < 2; t++) {
+        const double *s = params + 26 * t;
+        if (!(s[6] > 0) || !(s[11] > 0) || !(s[18] > 0) || !(s[12] > 0) || !(s[19] > 0) || !(s[22] > 0) ||
+            !(s[5] > s[4]) || !(s[23] > 0))
+            return fail(CTBOP_E_INVAL, "parameters: need sigma, n_l, g_l, J, gamma_coul > 0 and S > R");
+    }
+    if (!(params[55] > 0) || !(params[54] > 0)) return fail(CTBOP_E_INVAL, "parameters: need p > 0, rc > 0");
+    return CTBOP_OK;
 }
 
 int fill_info(ctbop_ctx *ctx, Prep &P, ctbop_info *info)
@@ -511,15 +532,9 @@ void ctbop_default_opts(ctbop_opts *o)
 
 int ctbop_create(const double *params, int n_params, const ctbop_opts *opts, ctbop_ctx **out)
 {
-    if (!params || !out) return fail(CTBOP_E_INVAL, "null argument");
-    if (n_params != CTBOP_N_PARAMS) return fail(CTBOP_E_INVAL, "expected 56 parameters");
-    for (int t = 0; t < 2; t++) {
-        const double *s = params + 26 * t;
-        if (!(s[6] > 0) || !(s[11] > 0) || !(s[18] > 0) || !(s[12] > 0) || !(s[19] > 0) || !(s[22] > 0) ||
-            !(s[5] > s[4]) || !(s[23] > 0))
-            return fail(CTBOP_E_INVAL, "parameters: need sigma, n_l, g_l, J, gamma_coul > 0 and S > R");
-    }
-    if (!(params[55] > 0) || !(params[54] > 0)) return fail(CTBOP_E_INVAL, "parameters: need p > 0, rc > 0");
+    if (!out) return fail(CTBOP_E_INVAL, "null argument");
+    int prc = check_params(params, n_params);
+    if (prc) return prc;
     ctbop_ctx *c = new ctbop_ctx();
     memcpy(c->theta, params, sizeof c->theta);
     ctbop_default_opts(&c->opts);
@@ -541,6 +556,23 @@ int ctbop_create(const double *params, int n_params, const ctbop_opts *opts, ctb
     fill_params<float>(c->theta, c->opts, c->pf);
     fill_params<double>(c->theta, c->opts, c->pd);
     *out = c;
+    return CTBOP_OK;
+}
+
+int ctbop_set_params(ctbop_ctx *ctx, const double *params, int n_params)
+{
+    if (!ctx) return fail(CTBOP_E_INVAL, "null argument");
+    int rc = check_params(params, n_params);
+    if (rc) return rc;
+    if (ctx->servers.load() > 0) return fail(CTBOP_E_BUSY, "a server is running on this context");
+    memcpy(ctx->theta, params, sizeof ctx->theta);
+    fill_params<float>(ctx->theta, ctx->opts, ctx->pf);
+    fill_params<double>(ctx->theta, ctx->opts, ctx->pd);
+    ctx->param_gen++;
+    // list radii may have changed: every system buffer starts over
+    ctx->seen.clear();
+    ctx->last_iters.clear();
+    ctx->eval_gen.clear();
     return CTBOP_OK;
 }
 
@@ -742,3 +774,4 @@ int ctbop_debug_lists(ctbop_ctx *ctx, int n, void *sys, size_t sys_bytes, int lo
 } // extern "C"
 
 #include "server.h"
+#include "adjoint_host.h"

@@ -483,6 +483,7 @@ int ctbop_server_create(ctbop_ctx *ctx, void *arena, size_t arena_bytes, int max
         return fail(CTBOP_E_HIP, "pinned host tables");
     }
     S->th = std::thread(server_loop, S);
+    ctx->servers++;
     *out = S;
     return CTBOP_OK;
 }
@@ -563,6 +564,7 @@ int ctbop_server_destroy(ctbop_server *S)
     if (S->htiles) (void)hipHostFree(S->htiles);
     if (S->hids) (void)hipHostFree(S->hids);
     if (S->hflags) (void)hipHostFree(S->hflags);
+    S->ctx->servers--;
     delete S;
     return CTBOP_OK;
 }

@@ -67,4 +67,16 @@ def test_bad_arguments_rejected_on_host(L, theta):
                                                pbc.ctypes.data, 0.0, 0, ctypes.c_void_p(256), nb.value - 1,
                                                None, ctypes.c_void_p(8), ctypes.c_void_p(8), None, None)
     assert rc == ct.E_NOMEM
+    # parameter replacement: the same checks as create
+    assert L.ctbop_set_params(h, bad.ctypes.data, 56) == ct.E_INVAL
+    assert L.ctbop_set_params(h, theta.ctypes.data, 56) == 0
+    # the adjoint: workspace size, and no preceding evaluation on this buffer
+    ab = ctypes.c_size_t()
+    assert L.ctbop_param_grad_bytes(h, 1000, box.ctypes.data, pbc.ctypes.data, ctypes.byref(ab)) == 0
+    assert ab.value > 1000 * 64 * 6 * 8
+    g = np.zeros(56)
+    rc = L.ctbop_param_grad(h, 1000, box.ctypes.data, pbc.ctypes.data, ctypes.c_void_p(256), nb.value,
+                            ctypes.c_void_p(256), ab.value, 1.0, ctypes.c_void_p(8), None, g.ctypes.data, None,
+                            None)
+    assert rc == ct.E_INVAL and b"preceding evaluation" in L.ctbop_last_error()
     L.ctbop_destroy(h)
