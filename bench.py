@@ -16,6 +16,7 @@ all inputs resident in HBM.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -200,6 +201,109 @@ def serving_bench(pot_factory, reqs, qps_fracs=(0.9,), baseline_count=None, aren
     return out
 
 
+def fit_bench(ct, theta, count: int = 256, fd_configs: int = 16):
+    """Force-matching fit batch: `count` fit-set structures (strained 3C-SiC,
+    graphene with Stone-Wales defects, amorphous C; 64-2000 atoms), reference
+    forces from the FP64 path at the base parameters, the loss
+    sum |F(theta') - F_ref|^2 at parameters perturbed by up to 5 % (cut-offs
+    kept, J only upwards).  Timed: forward + adjoint (mixed precision) over
+    the whole batch.  Checked: the FP64 adjoint gradient of the loss over the
+    first `fd_configs` structures against central differences of the FP64
+    forward, for a few parameters."""
+    import numpy as np
+    import torch
+    from ctbop_inputs import generators as G
+    from ctbop_inputs import params as PR
+    batch = G.fit_batch(count, seed=1003)
+    rng = np.random.Generator(np.random.PCG64(1007))
+    th = theta * (1.0 + rng.uniform(-0.05, 0.05, size=theta.shape))
+    th[[4, 5, 30, 31, 54]] = theta[[4, 5, 30, 31, 54]]
+    th[[22, 48]] = theta[[22, 48]] * (1.0 + rng.uniform(0.0, 0.05, size=2))
+    dev = "cuda"
+
+    def dev_inputs(s):
+        return (torch.tensor(s.pos.T.copy().reshape(-1), dtype=torch.float64, device=dev),
+                torch.tensor(s.types, dtype=torch.int32, device=dev))
+
+    inputs = [dev_inputs(s) for s in batch]
+    ref_pot = ct.Potential(theta, fp64=True)
+    F_ref = []
+    for s, (x, ty) in zip(batch, inputs):
+        _, F, _, _ = ref_pot.compute_soa(x, ty, s.box, s.pbc, warm=False, sysbuf=ct.System(ref_pot, s.n, s.box, s.pbc),
+                                         want_info=False)
+        F_ref.append(F.clone())
+    sizes = []
+    for s in batch:
+        b, p = ct._box_pbc(s.box, s.pbc)
+        nb = ctypes.c_size_t()
+        ct._check(ct.lib().ctbop_param_grad_bytes(ref_pot.ctx, s.n, b.ctypes.data, p.ctypes.data, ctypes.byref(nb)))
+        sizes.append(nb.value)
+    ws = torch.empty(max(sizes), dtype=torch.uint8, device=dev)
+
+    def batch_grad(pot, idx, sysbufs):
+        loss, grad, it = 0.0, np.zeros(len(theta)), 0
+        for k in idx:
+            s = batch[k]
+            x, ty = inputs[k]
+            _, F, _, _ = pot.compute_soa(x, ty, s.box, s.pbc, warm=False, force_rebuild=True, sysbuf=sysbufs[k],
+                                         want_info=False)
+            d = F - F_ref[k]
+            loss += float((d * d).sum())
+            g, ni = pot.param_grad(sysbufs[k], s.box, s.pbc, 0.0, 2.0 * d, None, ws=ws)
+            grad += g
+            it += ni
+        return loss, grad, it
+
+    pot = ct.Potential(th)
+    bufs = [ct.System(pot, s.n, s.box, s.pbc) for s in batch]
+    batch_grad(pot, range(min(8, count)), bufs)             # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    # forward alone, then forward + adjoint (lists rebuilt every call, as
+    # after a parameter update)
+    for k, s in enumerate(batch):
+        x, ty = inputs[k]
+        pot.compute_soa(x, ty, s.box, s.pbc, warm=False, force_rebuild=True, sysbuf=bufs[k], want_info=False)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    loss, grad, adj_iters = batch_grad(pot, range(count), bufs)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    natoms = sum(s.n for s in batch)
+    # gradient check: FP64 adjoint vs central differences of the FP64 forward
+    pot64 = ct.Potential(th, fp64=True, cg_tol=1e-13)
+    idx = range(min(fd_configs, count))
+    bufs64 = {k: ct.System(pot64, batch[k].n, batch[k].box, batch[k].pbc) for k in idx}
+    _, g64, _ = batch_grad(pot64, idx, bufs64)
+    names = PR.names()
+    check = {}
+    for nm in ("Si.B", "C.lam2", "C.ch1.c", "C.ch2.n", "p", "Si.chi", "Si.gamma_coul", "ke"):
+        k = names.index(nm)
+        h = 1e-5 * abs(th[k])
+        vals = []
+        for sgn in (1, -1):
+            t2 = th.copy()
+            t2[k] += sgn * h
+            pot64.set_params(t2)
+            bb = {j: ct.System(pot64, batch[j].n, batch[j].box, batch[j].pbc) for j in idx}
+            tot = 0.0
+            for j in idx:
+                x, ty = inputs[j]
+                _, F, _, _ = pot64.compute_soa(x, ty, batch[j].box, batch[j].pbc, warm=False, sysbuf=bb[j],
+                                               want_info=False)
+                d = F - F_ref[j]
+                tot += float((d * d).sum())
+            vals.append(tot)
+        fd = (vals[0] - vals[1]) / (2 * h)
+        check[nm] = {"adjoint": float(g64[k]), "fd": fd, "rel_err": abs(g64[k] - fd) / max(abs(fd), 1e-300)}
+    return {"configs": count, "atoms": natoms, "loss": loss, "grad_norm": float(np.linalg.norm(grad)),
+            "forward_s": t_fwd, "forward_adjoint_s": t_all, "configs_per_s": count / t_all,
+            "atoms_per_s": natoms / t_all, "adjoint_cg_iters_mean": adj_iters / count,
+            "dtype": "f32-terms/f64-sums", "fd_check_fp64": {"configs": len(idx), "params": check,
+                                                             "max_rel_err": max(c["rel_err"] for c in check.values())}}
+
+
 def cpu_baseline(theta, nx: int, nsteps: int):
     """The CPU oracle (FP64, OpenMP) on a bounded sample of the same workload:
     the same stepped, depleted slab at nx x nx cells, nsteps MD steps."""
@@ -234,6 +338,7 @@ def main():
                     help="serving benchmark only: 4096 Poisson requests at 5 loads vs per-request launches")
     ap.add_argument("--serve-requests", type=int, default=None)
     ap.add_argument("--no-serving", action="store_true", help="skip the compact serving measurement")
+    ap.add_argument("--no-fit", action="store_true", help="skip the fit-batch (parameter gradient) measurement")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (scales HBM byte counters)")
     args = ap.parse_args()
@@ -294,7 +399,6 @@ def main():
     sysb = pot.system(n, s.box, s.pbc)
     b, p = ct._box_pbc(s.box, s.pbc)
     L = ct.lib()
-    import ctypes
 
     def run(nsteps):
         info = ct.Info()
@@ -373,6 +477,10 @@ def main():
         torch.cuda.empty_cache()
         out["serving"] = serving_bench(lambda: ct.Potential(theta), reqs, qps_fracs=(0.9,), baseline_count=128,
                                        arena_gb=16)
+    if not args.no_fit:
+        print("bench: fit-batch forward + adjoint", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        out["fit_batch"] = fit_bench(ct, theta)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(theta, args.cpu_nx, args.cpu_steps)
