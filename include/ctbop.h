@@ -118,6 +118,7 @@ typedef struct {
     int    n_rebuild;   /* list rebuilds since this system buffer was set up   */
     unsigned long long cg_iters_total;  /* charge-solve iterations since set-up */
     double cg_res0;     /* starting RMS projected residual of the last solve   */
+    unsigned long long nnz_coul;  /* Coulomb entries inside rc at the last assembly */
 } ctbop_info;
 
 /* Fill *o with the defaults above. */
@@ -204,7 +205,8 @@ int ctbop_status(ctbop_ctx *ctx, void *sys_dev, size_t sys_bytes, void *stream, 
  * clears them if reset != 0, then turns timing on (enable != 0) or off.
  * Classes: 0 charge-solve matrix-vector product, 1 Coulomb force/energy
  * gather, 2 Coulomb matrix assembly, 3 covalent bond pass, 4 covalent force
- * gather, 5 charge-solve update, 6 charge-solve direction, 7 list build. */
+ * gather, 5 charge-solve update, 6 charge-solve direction, 7 list build,
+ * 8 sliced copy of the Coulomb rows. */
 int ctbop_profile(ctbop_ctx *ctx, int enable, int reset, void *stream, double *ms_out, long *count_out, int nk);
 
 /* Message of the last error on the calling thread ("" if none). */

@@ -44,7 +44,8 @@ class Info(ctypes.Structure):
                 ("cg_iters", ctypes.c_int), ("rebuilt", ctypes.c_int), ("status", ctypes.c_int),
                 ("max_long", ctypes.c_int), ("max_short", ctypes.c_int),
                 ("nnz_long", ctypes.c_ulonglong), ("nnz_short", ctypes.c_ulonglong), ("n_rebuild", ctypes.c_int),
-                ("cg_iters_total", ctypes.c_ulonglong), ("cg_res0", ctypes.c_double)]
+                ("cg_iters_total", ctypes.c_ulonglong), ("cg_res0", ctypes.c_double),
+                ("nnz_coul", ctypes.c_ulonglong)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -257,7 +258,7 @@ class Potential:
         return (x.reshape(3, n).t().contiguous(), v.reshape(3, n).t().contiguous(),
                 F.reshape(3, n).t().contiguous(), q, thermo, info.as_dict())
 
-    KERNELS = ("spmv", "force_coul", "assemble", "bond", "force_cov", "cg_update", "cg_dir", "build")
+    KERNELS = ("spmv", "force_coul", "assemble", "bond", "force_cov", "cg_update", "cg_dir", "build", "hslice")
 
     def profile(self, enable=True, reset=True):
         """Per-kernel event timing: returns {name: (ms_total, launches)} accumulated

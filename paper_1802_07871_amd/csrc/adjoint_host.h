@@ -141,7 +141,7 @@ int launch_param_grad(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, char *adj, 
     for (;;) {
         for (int c = 0; c < ctx->opts.cg_check; c++) {
             hipLaunchKernelGGL(k_cg_dir, g, b, 0, st, P.dtiles, dadj);
-            hipLaunchKernelGGL((k_spmv<R, SPMV_LPR, SPMV_U>), g, b, 0, st, P.dtiles, dadj);
+            hipLaunchKernelGGL((k_spmv<R, SPMV_U>), g, b, 0, st, P.dtiles, dadj);
             hipLaunchKernelGGL(k_fin_alpha, g1, b, 0, st, sid, dadj);
             hipLaunchKernelGGL(k_cg_update, g, b, 0, st, P.dtiles, dadj);
             hipLaunchKernelGGL(k_fin_update, g1, b, 0, st, sid, dadj, ctl);

@@ -25,9 +25,8 @@ using namespace ctbop;
 
 namespace {
 
-constexpr int LPR = 16;             // lanes per Coulomb-list row (assembly, force gather)
-constexpr int SPMV_LPR = 32;        // lanes per row in the charge-solve product (tuned)
-constexpr int SPMV_U = 2;           // independent entries per lane per step (tuned)
+constexpr int LPR = 16;             // lanes per Coulomb row (assembly, force gather)
+constexpr int SPMV_U = 8;           // list entries in flight per row in the charge-solve product (tuned)
 
 thread_local std::string g_err;
 
@@ -192,7 +191,7 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
     S.npad = (n + TILE - 1) / TILE * TILE;
     S.ntile = S.npad / TILE;
     S.tile0 = 0;
-    S.Wl = (ctx->opts.long_cap + 3) / 4 * 4;     // 16-byte aligned rows for vector loads
+    S.Wl = ctx->opts.long_cap;
     S.Ws = ctx->opts.short_cap;
     S.skin = ctx->opts.skin;
     const int fp64 = ctx->opts.fp64;
@@ -214,6 +213,8 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
     size_t o_off = take(8 * 3 * np), o_ref = take(8 * 3 * (size_t)n), o_xs = take(v4 * np);
     size_t o_xs64 = fp64 ? o_xs : take(32 * np);
     size_t o_lcnt = take(4 * np), o_lidx = take(4 * np * S.Wl), o_H = take(rsz * np * S.Wl);
+    size_t o_hcnt = take(4 * np), o_hidx = take(4 * np * S.Wl), o_Hr = take(rsz * np * S.Wl);
+    size_t o_hsidx = take(4 * np * S.Wl);
     size_t o_scnt = take(4 * np), o_sidx = take(4 * np * S.Ws), o_srev = take(np * S.Ws), o_slot = take(v4 * np * S.Ws);
     size_t o_ecov = take(8 * np), o_fcov = take(8 * 3 * np);
     size_t o_q = take(8 * np), o_r = take(8 * np), o_p = take(8 * np), o_s = take(8 * np), o_d = take(8 * np),
@@ -235,6 +236,10 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
         S.lcnt = (int *)(base + o_lcnt);
         S.lidx = (uint32_t *)(base + o_lidx);
         S.H = base + o_H;
+        S.hcnt = (int *)(base + o_hcnt);
+        S.hidx = (uint32_t *)(base + o_hidx);
+        S.Hr = base + o_Hr;
+        S.hsidx = (uint32_t *)(base + o_hsidx);
         S.scnt = (int *)(base + o_scnt);
         S.sidx = (uint32_t *)(base + o_sidx);
         S.srev = (uint8_t *)(base + o_srev);
@@ -424,6 +429,10 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
         Timed t(ctx, 2, st);
         hipLaunchKernelGGL((k_assemble<R, LPR>), g, b, 0, st, P.dtiles, P.dseg, ctx->pd);
     }
+    {
+        Timed t(ctx, 8, st);
+        hipLaunchKernelGGL((k_hslice<R>), g, b, 0, st, P.dtiles, P.dseg);
+    }
     hipLaunchKernelGGL(k_fin_w0, g1, b, 0, st, sid, P.dseg);
     hipLaunchKernelGGL(k_shift_stats, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_fin_assemble, g1, b, 0, st, sid, P.dseg, ctl);
@@ -439,7 +448,7 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
             }
             {
                 Timed t(ctx, 0, st);
-                hipLaunchKernelGGL((k_spmv<R, SPMV_LPR, SPMV_U>), g, b, 0, st, P.dtiles, P.dseg);
+                hipLaunchKernelGGL((k_spmv<R, SPMV_U>), g, b, 0, st, P.dtiles, P.dseg);
             }
             hipLaunchKernelGGL(k_fin_alpha, g1, b, 0, st, sid, P.dseg);
             {
@@ -511,6 +520,7 @@ int fill_info(ctbop_ctx *ctx, Prep &P, ctbop_info *info)
     info->n_rebuild = ss.nrebuild;
     info->cg_iters_total = ss.iters_total;
     info->cg_res0 = ss.res0;
+    info->nnz_coul = (unsigned long long)ss.nnz_coul;
     if (ss.status) return fail(info->status, status_text(ss.status));
     return CTBOP_OK;
 }

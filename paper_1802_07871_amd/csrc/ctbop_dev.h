@@ -21,6 +21,7 @@ constexpr uint32_t J_MASK = (1u << CODE_SHIFT) - 1u;
 constexpr int NCODE = 343;             // offsets (-3..3)^3
 constexpr int CODE_CENTER = 171;       // offset (0,0,0)
 constexpr int MAX_ATOMS = (1 << CODE_SHIFT) - 1;
+constexpr int SLICE = 64;              // rows per slice of the sliced list layout (one wave)
 
 // status bits (mapped to CTBOP_E_* codes on the host)
 constexpr int ST_TOO_CLOSE = 1, ST_NOCONV = 2, ST_NOT_PD = 4, ST_OVERFLOW = 8, ST_REV = 16;
@@ -71,6 +72,7 @@ struct SegState {
     unsigned long long nnz_long, nnz_short;   // list entries at the last build
     unsigned long long iters_total;           // charge-solve iterations since set-up
     double res0;                              // starting residual of the last solve
+    double nnz_coul;                          // Coulomb entries inside rc at the last assembly
 };
 
 // ---------------------------------------------------------------------------
@@ -105,8 +107,20 @@ struct Seg {
     double *ref_x;     // user order positions at build, SoA [3n]
     void *xs;          // sorted local coordinates + type  [npad] float4 / double4
     double4 *xs64;     // the same in FP64 (bond lengths of the energy)  [npad]
+    // Coulomb list: r < rc + skin at the last build, row-major, stride Wl.
     int *lcnt;         // [npad]
     uint32_t *lidx;    // [npad * Wl]
+    // Coulomb rows of the current step (rewritten by every assembly): the
+    // list entries inside rc in list order, row-major (hidx, with the
+    // matrix entries Hr), and the same rows sliced column-major for the
+    // charge-solve product (hsidx, H): slices of SLICE consecutive rows, entry
+    // e of row s at (s / SLICE) * SLICE * Wl + e * SLICE + s % SLICE, so that
+    // a wave, one row per lane, reads entry e of its 64 rows as one
+    // contiguous segment.
+    int *hcnt;         // [npad]
+    uint32_t *hidx;    // [npad * Wl]
+    void *Hr;          // [npad * Wl] float / double
+    uint32_t *hsidx;   // [npad * Wl]
     void *H;           // [npad * Wl] float / double
     int *scnt;         // [npad]
     uint32_t *sidx;    // [npad * Ws]
@@ -149,6 +163,12 @@ template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };
 template <> struct Vec4<double> { using type = double4; };
 
+// Offset of entry 0 of row s in a sliced list of width W (entry e adds e * SLICE)
+__device__ __forceinline__ size_t slice_base(int s, int W)
+{
+    return (size_t)(s & ~(SLICE - 1)) * (size_t)W + (size_t)(s & (SLICE - 1));
+}
+
 __device__ __forceinline__ int code_of(int d0, int d1, int d2) { return ((d0 + 3) * 7 + (d1 + 3)) * 7 + (d2 + 3); }
 
 // reverse offset code: (-d0, -d1, -d2)
@@ -169,6 +189,44 @@ __device__ __forceinline__ double group_sum(double v)
 #pragma unroll
     for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
     return v;
+}
+
+template <int W>
+__device__ __forceinline__ int group_sumi(int v)
+{
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+    return v;
+}
+
+// The W-bit slice of a wave ballot that belongs to this lane's group of W
+// consecutive lanes (W a power of two <= 32).
+template <int W>
+__device__ __forceinline__ unsigned group_ballot(bool pred)
+{
+    const unsigned long long m = __ballot(pred);
+    const int base = (int)(threadIdx.x & 63) & ~(W - 1);
+    const unsigned all = (W == 32) ? 0xffffffffu : ((1u << W) - 1u);
+    return (unsigned)(m >> base) & all;
+}
+
+// Exclusive prefix sum of one int per thread over the 256-thread block, in a
+// fixed order; every thread of the block must call it.
+__device__ __forceinline__ int block_excl_scan(int v, int *lds /* 4 */)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[wv] = x;
+    __syncthreads();
+    int off = 0;
+    for (int w = 0; w < wv; w++) off += lds[w];
+    __syncthreads();
+    return off + x - v;
 }
 
 template <int W>

@@ -73,16 +73,16 @@ __global__ void __launch_bounds__(TILE) k_adj_source(const Tile *tiles, Seg *seg
         const V4 li = xs[s];
         const int ti = (int)li.w;
         const double vx = A.v[s], vy = A.v[S.npad + s], vz = A.v[2 * S.npad + s];
-        const int cnt = S.lcnt[s];
-        const uint32_t *row = S.lidx + (size_t)s * S.Wl;
+        const int cnt = S.hcnt[s];
+        const uint32_t *row = S.hidx + (size_t)s * S.Wl;
         double acc = 0.0;
         for (int e = lane; e < cnt; e += LPR) {
             const uint32_t ent = row[e];
             const int j = (int)(ent & J_MASK);
             if (j == s) continue;
             const V4 lj = xs[j];
-            const R3<R> d = pair_vec<R>(li, lj, dtab[ent >> CODE_SHIFT]);
-            const double r = (double)dev_sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
+            R3<R> d;
+            const double r = entry_r<R>(li, lj, dtab[ent >> CODE_SHIFT], d);
             if (r >= PD.rc) continue;
             double dC;
             coul64(PD, ti * 2 + (int)lj.w, r, dC);
@@ -334,15 +334,15 @@ __global__ void __launch_bounds__(TILE) k_coul_dual(const Tile *tiles, Seg *segs
         const int ti = (int)li.w;
         const double qs = S.q[s] + qsh, ls = A.lam[s] + lsh;
         const double vx = A.v[s], vy = A.v[S.npad + s], vz = A.v[2 * S.npad + s];
-        const int cnt = S.lcnt[s];
-        const uint32_t *row = S.lidx + (size_t)s * S.Wl;
+        const int cnt = S.hcnt[s];
+        const uint32_t *row = S.hidx + (size_t)s * S.Wl;
         double acc = 0.0;
         for (int e = lane; e < cnt; e += LPR) {
             const uint32_t ent = row[e];
             const int j = (int)(ent & J_MASK);
             const V4 lj = xs[j];
-            const R3<R> d = pair_vec<R>(li, lj, dtab[ent >> CODE_SHIFT]);
-            const double r = (double)dev_sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
+            R3<R> d;
+            const double r = entry_r<R>(li, lj, dtab[ent >> CODE_SHIFT], d);
             if (r >= P.rc.v) continue;
             Dual dC;
             const Dual c = coul_dual(P, ti * 2 + (int)lj.w, r, dC);

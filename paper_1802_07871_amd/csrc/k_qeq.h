@@ -12,9 +12,11 @@
 // dot products and the projection are FP64; the matrix entries are stored in
 // the pair precision (FP32 in the mixed build).
 //
-// Rows of the Coulomb list are processed by LPR consecutive lanes each; rows
-// are stored row-major (stride Wl), so the lanes of a row read contiguous
-// memory and their partial sums combine by a fixed butterfly.
+// Assembly and the force gather give each row LPR consecutive lanes, which
+// read consecutive entries (neighbours in one cell, so their coordinates are
+// gathered together) and combine by a fixed butterfly.  The charge-solve
+// product runs one row per lane over a sliced copy of the rows, made once per
+// step, where entry e of 64 consecutive rows is one contiguous segment.
 #pragma once
 #include "ctbop_dev.h"
 #include "k_tersoff.h"
@@ -57,8 +59,20 @@ struct CgCtl {
     int maxit;
 };
 
-// Assemble the Coulomb entries of every row, the diagonal (J plus self
-// images) and the starting residual r = -(H q0 + chi) + mu_prev.
+// Distance of a list entry, in the pair precision R and then widened: every
+// kernel that tests it against rc computes it this one way, so all of them
+// agree on which entries lie inside.
+template <typename R>
+__device__ __forceinline__ double entry_r(const typename Vec4<R>::type &li, const typename Vec4<R>::type &lj,
+                                          const typename Vec4<R>::type &D, R3<R> &d)
+{
+    d = pair_vec<R>(li, lj, D);
+    return (double)dev_sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
+}
+
+// Assemble the Coulomb rows of the step: the list entries inside rc, in list
+// order, into hidx/Hr (group ballots give each lane its slot), the diagonal
+// (J plus self images) and the starting residual r = -(H q0 + chi) + mu_prev.
 template <typename R, int LPR>
 __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs, Params<double> PD)
 {
@@ -69,30 +83,51 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
     __shared__ double lds[4 * 5];
     load_dtab2<R>(S, dtab);
     const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
-    R *H = reinterpret_cast<R *>(S.H);
+    R *Hr = reinterpret_cast<R *>(S.Hr);
     const double mprev = S.sst->mu_prev;
     constexpr int G = TILE / LPR;
     const int lane = threadIdx.x % LPR;
+    const unsigned below = (1u << lane) - 1u;
     double acc5[5] = {0, 0, 0, 0, 0};
     for (int k = threadIdx.x / LPR; k < TILE; k += G) {
         const int s = T.row0 + k;
-        if (s >= S.n) continue;
+        if (s >= S.n) {
+            if (s < S.npad && lane == 0) S.hcnt[s] = 0;
+            continue;                          // the whole group skips together
+        }
         const V4 li = xs[s];
         const int ti = (int)li.w;
         const int cnt = S.lcnt[s];
         const uint32_t *row = S.lidx + (size_t)s * S.Wl;
-        R *hrow = H + (size_t)s * S.Wl;
+        uint32_t *hrow = S.hidx + (size_t)s * S.Wl;
+        R *vrow = Hr + (size_t)s * S.Wl;
         double acc = 0.0, self = 0.0;
-        for (int e = lane; e < cnt; e += LPR) {
-            const uint32_t ent = row[e];
-            const int j = (int)(ent & J_MASK);
-            const V4 lj = xs[j];
-            const R3<R> d = pair_vec<R>(li, lj, dtab[ent >> CODE_SHIFT]);
-            const double r = (double)dev_sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
-            const R c = r < PD.rc ? (R)coul64_val(PD, ti * 2 + (int)lj.w, r) : (R)0;
-            hrow[e] = c;
-            acc += (double)c * S.q[j];
-            if (j == s) self += (double)c;
+        int pos = 0;
+        for (int e0 = 0; e0 < cnt; e0 += LPR) {
+            const int e = e0 + lane;
+            bool in = false;
+            uint32_t ent = 0;
+            int j = 0, tj = 0;
+            double r = 0.0;
+            if (e < cnt) {
+                ent = row[e];
+                j = (int)(ent & J_MASK);
+                const V4 lj = xs[j];
+                tj = (int)lj.w;
+                R3<R> d;
+                r = entry_r<R>(li, lj, dtab[ent >> CODE_SHIFT], d);
+                in = r < PD.rc;
+            }
+            const unsigned gm = group_ballot<LPR>(in);
+            if (in) {
+                const int at = pos + __popc(gm & below);
+                const R c = (R)coul64_val(PD, ti * 2 + tj, r);
+                hrow[at] = ent;
+                vrow[at] = c;
+                acc += (double)c * S.q[j];
+                if (j == s) self += (double)c;
+            }
+            pos += __popc(gm);
         }
         acc = group_sum<LPR>(acc);
         self = group_sum<LPR>(self);
@@ -100,15 +135,63 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
             const double qs = S.q[s];
             const double di = 1.0 / (PD.J[ti] + self);
             const double r = -(PD.J[ti] * qs + acc + PD.chi[ti]) + mprev;
+            S.hcnt[s] = pos;
             S.dinv[s] = di;
             S.jd[s] = PD.J[ti];
             S.r[s] = r;
             S.p[s] = 0.0;
             acc5[0] += r * di;
+            acc5[1] += (double)pos;
             acc5[4] += di;
         }
     }
     tile_partials<5>(S, T.row0 / TILE, acc5, lds);
+}
+
+// Sliced copy (hsidx, H) of the step's rows (hidx, Hr) for the charge-solve
+// product.  Each block transposes its tile through LDS in chunks of HS_CH
+// entries: HS_CH lanes read a row segment, then each lane writes its row's
+// chunk as slice columns; both sides touch contiguous memory.
+constexpr int HS_CH = 16;
+template <typename R>
+__global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
+{
+    const Tile T = my_tile(tiles);
+    const Seg &S = segs[T.seg];
+    __shared__ uint32_t ci[TILE][HS_CH + 1];
+    __shared__ R cv[TILE][HS_CH + 1];
+    __shared__ int cnt_lds[TILE];
+    __shared__ int mx[4];
+    const int own = T.row0 + threadIdx.x;
+    const int own_cnt = own < S.n ? S.hcnt[own] : 0;
+    cnt_lds[threadIdx.x] = own_cnt;
+    int m = own_cnt;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) mx[threadIdx.x >> 6] = m;
+    __syncthreads();
+    const int maxc = max(max(mx[0], mx[1]), max(mx[2], mx[3]));
+    const R *Hr = reinterpret_cast<const R *>(S.Hr);
+    R *H = reinterpret_cast<R *>(S.H);
+    const int lane = threadIdx.x % HS_CH;
+    const size_t b0 = slice_base(own, S.Wl);
+    for (int E0 = 0; E0 < maxc; E0 += HS_CH) {
+        for (int k = threadIdx.x / HS_CH; k < TILE; k += TILE / HS_CH) {
+            const int e = E0 + lane;
+            if (e < cnt_lds[k]) {
+                const size_t at = (size_t)(T.row0 + k) * S.Wl + e;
+                ci[k][lane] = S.hidx[at];
+                cv[k][lane] = Hr[at];
+            }
+        }
+        __syncthreads();
+        const int lim = min(HS_CH, own_cnt - E0);
+        for (int e = 0; e < lim; e++) {
+            S.hsidx[b0 + (size_t)(E0 + e) * SLICE] = ci[threadIdx.x][e];
+            H[b0 + (size_t)(E0 + e) * SLICE] = cv[threadIdx.x][e];
+        }
+        __syncthreads();
+    }
 }
 
 // First pass over the starting residual: its D-weighted mean w0.
@@ -122,6 +205,7 @@ __global__ void k_fin_w0(const int *seg_ids, Seg *segs)
         SegState *st = S.sst;
         st->sdinv = tot[4];
         st->w = tot[0] / tot[4];
+        st->nnz_coul = tot[1];
     }
 }
 
@@ -185,47 +269,47 @@ __global__ void __launch_bounds__(TILE) k_cg_dir(const Tile *tiles, Seg *segs)
     S.p[s] = S.dinv[s] * r + beta * S.p[s];
 }
 
-// s = H p and the tile's share of p^T s.  LPR lanes per row; lane l takes
-// entries l, l + LPR, ... so each load instruction reads consecutive entries
-// (and, rows being in cell order, mostly neighbouring p values); U entries
-// per lane per step keep U independent gathers in flight.  Entries past the
-// row's count are masked before their loads.
-template <typename R, int LPR, int U>
+// s = H p and the tile's share of p^T s, one row per lane; U entries of the
+// row are loaded before their products are summed, so U gathers of p are in
+// flight per lane (U accumulators, combined in a fixed order at the end).
+template <typename R, int U>
 __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
 {
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     if (S.sst->done) return;
     __shared__ double lds[4];
-    const R *H = reinterpret_cast<const R *>(S.H);
-    const double *p = S.p;
-    constexpr int G = TILE / LPR;
-    const int lane = threadIdx.x % LPR;
+    const int s = T.row0 + threadIdx.x;
     double pap = 0.0;
-    for (int k = threadIdx.x / LPR; k < TILE; k += G) {
-        const int s = T.row0 + k;
-        if (s >= S.n) continue;
-        const int cnt = S.lcnt[s];
-        const uint32_t *row = S.lidx + (size_t)s * S.Wl;
-        const R *hrow = H + (size_t)s * S.Wl;
-        double acc = 0.0;
-        for (int e = lane; e < cnt; e += U * LPR) {
-            double a[U];
+    if (s < S.n) {
+        const double *p = S.p;
+        const size_t b0 = slice_base(s, S.Wl);
+        const uint32_t *row = S.hsidx + b0;
+        const R *hrow = reinterpret_cast<const R *>(S.H) + b0;
+        const int cnt = S.hcnt[s];
+        double acc[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) acc[u] = 0.0;
+        int e = 0;
+        for (; e + U <= cnt; e += U) {
+            uint32_t jj[U];
+            R hh[U];
 #pragma unroll
             for (int u = 0; u < U; u++) {
-                const int ee = e + u * LPR;
-                a[u] = (ee < cnt) ? (double)hrow[ee] * p[row[ee] & J_MASK] : 0.0;
+                jj[u] = row[(size_t)(e + u) * SLICE];
+                hh[u] = hrow[(size_t)(e + u) * SLICE];
             }
 #pragma unroll
-            for (int u = 0; u < U; u++) acc += a[u];
+            for (int u = 0; u < U; u++) acc[u] += (double)hh[u] * p[jj[u] & J_MASK];
         }
-        acc = group_sum<LPR>(acc);
-        if (lane == 0) {
-            const double ps = p[s];
-            const double y = S.jd[s] * ps + acc;
-            S.s[s] = y;
-            pap += ps * y;
-        }
+        for (; e < cnt; e++) acc[0] += (double)hrow[(size_t)e * SLICE] * p[row[(size_t)e * SLICE] & J_MASK];
+        double a = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; u++) a += acc[u];
+        const double ps = p[s];
+        const double y = S.jd[s] * ps + a;
+        S.s[s] = y;
+        pap = ps * y;
     }
     double v[1] = {pap};
     tile_partials<1>(S, T.row0 / TILE, v, lds);
@@ -325,16 +409,16 @@ __global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *seg
         if (s >= S.n) continue;
         const V4 li = xs[s];
         const int ti = (int)li.w;
-        const int cnt = S.lcnt[s];
-        const uint32_t *row = S.lidx + (size_t)s * S.Wl;
+        const int cnt = S.hcnt[s];
+        const uint32_t *row = S.hidx + (size_t)s * S.Wl;
         double ec = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
         for (int e = lane; e < cnt; e += LPR) {
             const uint32_t ent = row[e];
             const int j = (int)(ent & J_MASK);
             const V4 lj = xs[j];
-            const R3<R> d = pair_vec<R>(li, lj, dtab[ent >> CODE_SHIFT]);
-            const double r = (double)dev_sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
-            if (r >= PD.rc) continue;
+            R3<R> d;
+            const double r = entry_r<R>(li, lj, dtab[ent >> CODE_SHIFT], d);
+            if (r >= PD.rc) continue;          // never taken: the rows hold entries inside rc
             double dC;
             const double c = coul64(PD, ti * 2 + (int)lj.w, r, dC);
             const double qj = S.q[j] + qsh;

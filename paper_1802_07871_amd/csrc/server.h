@@ -297,6 +297,7 @@ int server_tick(ctbop_server *S, const Params<R> &prm)
         hipLaunchKernelGGL(k_mark_built, dim3((nis + 63) / 64), dim3(64), 0, st, sid, S->dsegs, nis);
         hipLaunchKernelGGL((k_bond<R>), g, b, 0, st, T, S->dsegs, ctx->pd);
         hipLaunchKernelGGL((k_assemble<R, LPR>), g, b, 0, st, T, S->dsegs, ctx->pd);
+        hipLaunchKernelGGL((k_hslice<R>), g, b, 0, st, T, S->dsegs);
         CgCtl ctl{ctx->opts.cg_tol, ctx->opts.cg_maxit};
         hipLaunchKernelGGL(k_fin_w0, gs, b, 0, st, sid, S->dsegs);
         hipLaunchKernelGGL(k_shift_stats, g, b, 0, st, T, S->dsegs);
@@ -309,7 +310,7 @@ int server_tick(ctbop_server *S, const Params<R> &prm)
         CgCtl ctl{ctx->opts.cg_tol, ctx->opts.cg_maxit};
         for (int c = 0; c < S->cg_per_tick; c++) {
             hipLaunchKernelGGL(k_cg_dir, g, b, 0, st, T, S->dsegs);
-            hipLaunchKernelGGL((k_spmv<R, SPMV_LPR, SPMV_U>), g, b, 0, st, T, S->dsegs);
+            hipLaunchKernelGGL((k_spmv<R, SPMV_U>), g, b, 0, st, T, S->dsegs);
             hipLaunchKernelGGL(k_fin_alpha, gs, b, 0, st, sid, S->dsegs);
             hipLaunchKernelGGL(k_cg_update, g, b, 0, st, T, S->dsegs);
             hipLaunchKernelGGL(k_fin_update, gs, b, 0, st, sid, S->dsegs, ctl);
