@@ -216,6 +216,8 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
     size_t o_hcnt = take(4 * np), o_hidx = take(4 * np * S.Wl), o_Hr = take(rsz * np * S.Wl);
     size_t o_hsidx = take(4 * np * S.Wl);
     size_t o_scnt = take(4 * np), o_sidx = take(4 * np * S.Ws), o_srev = take(np * S.Ws), o_slot = take(v4 * np * S.Ws);
+    size_t o_bcnt = take(4 * np), o_bidx = take(4 * np * S.Ws), o_cmap = take(np * S.Ws), o_bsrev = take(np * S.Ws),
+           o_brev = take(np * S.Ws);
     size_t o_ecov = take(8 * np), o_fcov = take(8 * 3 * np);
     size_t o_q = take(8 * np), o_r = take(8 * np), o_p = take(8 * np), o_s = take(8 * np), o_d = take(8 * np),
            o_jd = take(8 * np);
@@ -243,6 +245,11 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
         S.scnt = (int *)(base + o_scnt);
         S.sidx = (uint32_t *)(base + o_sidx);
         S.srev = (uint8_t *)(base + o_srev);
+        S.bcnt = (int *)(base + o_bcnt);
+        S.bidx = (uint32_t *)(base + o_bidx);
+        S.cmap = (uint8_t *)(base + o_cmap);
+        S.bsrev = (uint8_t *)(base + o_bsrev);
+        S.brev = (uint8_t *)(base + o_brev);
         S.slot = base + o_slot;
         S.ecov = (double *)(base + o_ecov);
         S.Fcov = (double *)(base + o_fcov);
@@ -420,6 +427,7 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
     }
     hipLaunchKernelGGL(k_rev, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_mark_built, g1, dim3(64), 0, st, sid, P.dseg, 1);
+    hipLaunchKernelGGL(k_bcompact, g, b, 0, st, P.dtiles, P.dseg, ctx->pd);
     {
         Timed t(ctx, 3, st);
         hipLaunchKernelGGL((k_bond<R>), g, b, 0, st, P.dtiles, P.dseg, ctx->pd);

@@ -122,10 +122,18 @@ struct Seg {
     void *Hr;          // [npad * Wl] float / double
     uint32_t *hsidx;   // [npad * Wl]
     void *H;           // [npad * Wl] float / double
+    // covalent list: r < S_ij + skin at the last build, row-major, stride Ws
     int *scnt;         // [npad]
     uint32_t *sidx;    // [npad * Ws]
-    uint8_t *srev;     // [npad * Ws]
-    void *slot;        // [npad * Ws] float4 / double4: b, P1, P2, -
+    uint8_t *srev;     // [npad * Ws]: slot of the reverse entry in the partner's row
+    // Bonds of the current step: the covalent-list entries inside S_ij (FP64
+    // distance), compacted in list order; cmap maps each list slot to its
+    // bond index (255: outside), bsrev is the list slot of the reverse entry,
+    // brev the bond index of the reverse bond in the partner's row.
+    int *bcnt;         // [npad]
+    uint32_t *bidx;    // [npad * Ws]
+    uint8_t *cmap, *bsrev, *brev;   // [npad * Ws]
+    void *slot;        // [npad * Ws] per bond, float4 / double4: b, P1, P2, -
     double *ecov;      // [npad]
     double *Fcov;      // SoA [3 npad]
     double *q, *r, *p, *s, *dinv, *jd;   // [npad]

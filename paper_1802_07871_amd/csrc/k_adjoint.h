@@ -140,11 +140,11 @@ __global__ void __launch_bounds__(TILE) k_bond_dual(const Tile *tiles, Seg *segs
     double ew = 0.0;
     if (s < S.n) {
         const double4 *xs = S.xs64;
-        const uint32_t *row = S.sidx + (size_t)s * S.Ws;
+        const uint32_t *row = S.bidx + (size_t)s * S.Ws;
         double *slot = A.slotd + (size_t)s * S.Ws * 6;
         const double4 li = xs[s];
         const int ti = (int)li.w;
-        const int ns = S.scnt[s];
+        const int ns = S.bcnt[s];
         Dual ecov(0.0);
         for (int e = 0; e < ns; e++) {
             const uint32_t ent = row[e];
@@ -213,8 +213,8 @@ __global__ void __launch_bounds__(TILE) k_force_cov_dual(const Tile *tiles, Seg 
         const double4 *xs = S.xs64;
         const double4 lm = xs[m];
         const int tm = (int)lm.w;
-        const int ns = S.scnt[m];
-        const uint32_t *row = S.sidx + (size_t)m * S.Ws;
+        const int ns = S.bcnt[m];
+        const uint32_t *row = S.bidx + (size_t)m * S.Ws;
         Dual fx(0.0), fy(0.0), fz(0.0);
         for (int e = 0; e < ns; e++) {
             const uint32_t ent = row[e];
@@ -257,13 +257,14 @@ __global__ void __launch_bounds__(TILE) k_force_cov_dual(const Tile *tiles, Seg 
             if (r2 >= P.Sc[pp].v * P.Sc[pp].v) continue;
             const double r = ::sqrt(r2), ir = 1.0 / r;
             const R3<double> d = {-dmi.x, -dmi.y, -dmi.z};
-            const int srev = S.srev[(size_t)m * S.Ws + e];
+            const int srev = S.brev[(size_t)m * S.Ws + e];
+            if (srev >= S.bcnt[i]) continue;                 // (a reverse always exists)
             const double *sv = A.slotd + ((size_t)i * S.Ws + srev) * 6;
             const Dual b = slotd_get(sv), P1 = slotd_get(sv + 2), P2 = slotd_get(sv + 4);
             const Dual dv = pair_dvdr<Dual>(P, pp, Dual(r), b) * ir;
             Dual ax = -dv * d.x, ay = -dv * d.y, az = -dv * d.z;
-            const int ni = S.scnt[i];
-            const uint32_t *rowi = S.sidx + (size_t)i * S.Ws;
+            const int ni = S.bcnt[i];
+            const uint32_t *rowi = S.bidx + (size_t)i * S.Ws;
             const R3<Dual> dd = {Dual(d.x), Dual(d.y), Dual(d.z)};
             for (int t = 0; t < ni; t++) {
                 if (t == srev) continue;

@@ -1,7 +1,7 @@
 // k_tersoff.h -- covalent part: bond pass and atomic-free force gather.
 //
-// Bond pass (one lane per sorted atom i): for every covalent-list entry
-// (i -> j) inside the cutoff S_ij, the environment sums of the two channels
+// Bond pass (one lane per sorted atom i): for every bond (i -> j), i.e. every
+// covalent-list entry inside the cutoff S_ij, the environment sums of the two channels
 //     zeta_l,ij = sum_{k != j} fc(r_ik) w_l(cos theta_ijk) exp[(alpha_l (r_ij - r_ik))^3]
 // (Methods, Eq. 2, one per channel), the vectorised bond order
 //     b_ij = G (sum_l (g_l + zeta_l^n_l)^-p)^(1/(2 sigma p))       (Eqs. 3-5, 7)
@@ -142,10 +142,50 @@ __device__ __forceinline__ void load_dtab2(const Seg &S, typename Vec4<R>::type 
     __syncthreads();
 }
 
+// Bonds of the step: the covalent-list entries inside S_ij, by the FP64
+// distance that the bond pass uses, compacted in list order.  Every loop
+// over bonds and triplets then runs over bonds only (the skin shell of the
+// covalent list, e.g. the twelve second neighbours of Si in SiC, drops out).
+__global__ void __launch_bounds__(TILE) k_bcompact(const Tile *tiles, Seg *segs, Params<double> P)
+{
+    const Tile T = my_tile(tiles);
+    const Seg &S = segs[T.seg];
+    __shared__ double4 dtab[NCODE];
+    load_dtab2<double>(S, dtab);
+    const int s = T.row0 + threadIdx.x;
+    if (s >= S.n) {
+        if (s < S.npad) S.bcnt[s] = 0;
+        return;
+    }
+    const double4 *xs = S.xs64;
+    const size_t rb = (size_t)s * S.Ws;
+    const double4 li = xs[s];
+    const int ti = (int)li.w;
+    const int ns = S.scnt[s];
+    int c = 0;
+    for (int e = 0; e < ns; e++) {
+        const uint32_t ent = S.sidx[rb + e];
+        const double4 lj = xs[ent & J_MASK];
+        const int pp = ti * 2 + (int)lj.w;
+        const R3<double> d = pair_vec<double>(li, lj, dtab[ent >> CODE_SHIFT]);
+        const double r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+        if (r2 < P.Sc[pp] * P.Sc[pp]) {
+            S.bidx[rb + c] = ent;
+            S.bsrev[rb + c] = S.srev[rb + e];
+            S.cmap[rb + e] = (uint8_t)c;
+            c++;
+        } else {
+            S.cmap[rb + e] = 255;
+        }
+    }
+    S.bcnt[s] = c;
+}
+
 // The bond pass runs in FP64 from the FP64 local coordinates: it is a small
 // share of the step (a few bonds per atom), and FP64 keeps the energy free of
 // FP32 rounding in zeta, b and the large, cancelling fR and b fA terms.  The
-// coefficients are stored in the pair precision R for the force gather.
+// coefficients are stored in the pair precision R for the force gather.  It
+// also resolves, per bond, the bond index of its reverse in the partner's row.
 template <typename R>
 __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Params<double> P)
 {
@@ -160,53 +200,51 @@ __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Par
         return;
     }
     const double4 *xs = S.xs64;
-    V4 *slot = reinterpret_cast<V4 *>(S.slot) + (size_t)s * S.Ws;
-    const uint32_t *row = S.sidx + (size_t)s * S.Ws;
+    const size_t rb = (size_t)s * S.Ws;
+    V4 *slot = reinterpret_cast<V4 *>(S.slot) + rb;
+    const uint32_t *row = S.bidx + rb;
     const double4 li = xs[s];
     const int ti = (int)li.w;
-    const int ns = S.scnt[s];
+    const int nb = S.bcnt[s];
     double ecov = 0.0;
-    for (int e = 0; e < ns; e++) {
+    for (int e = 0; e < nb; e++) {
         const uint32_t ent = row[e];
-        const double4 lj = xs[ent & J_MASK];
-        const int tj = (int)lj.w, pp = ti * 2 + tj;
+        const int j = (int)(ent & J_MASK);
+        const double4 lj = xs[j];
+        const int pp = ti * 2 + (int)lj.w;
         const R3<double> d = pair_vec<double>(li, lj, dtab[ent >> CODE_SHIFT]);
-        const double r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-        V4 out;
-        out.x = out.y = out.z = out.w = (R)0;
-        if (r2 < P.Sc[pp] * P.Sc[pp]) {
-            const double r = sqrt(r2);
-            double z1 = 0, z2 = 0;
-            for (int e2 = 0; e2 < ns; e2++) {
-                if (e2 == e) continue;
-                const uint32_t ent2 = row[e2];
-                const double4 lk = xs[ent2 & J_MASK];
-                const int pk = ti * 2 + (int)lk.w;
-                const R3<double> dk = pair_vec<double>(li, lk, dtab[ent2 >> CODE_SHIFT]);
-                const double rk2 = dk.x * dk.x + dk.y * dk.y + dk.z * dk.z;
-                if (rk2 >= P.Sc[pk] * P.Sc[pk]) continue;
-                const double rk = sqrt(rk2);
-                const double cs = (d.x * dk.x + d.y * dk.y + d.z * dk.z) / (r * rk);
-                double dummy, dw, dex;
-                const double fk = cutoff<double>(rk, P.Rc[pk], P.Sc[pk], P.piSR[pk], dummy);
-                double w1 = angular<double>(P, ti, 0, cs, dw), w2 = angular<double>(P, ti, 1, cs, dw);
-                if (!P.alpha_zero[ti]) {
-                    w1 *= radial<double>(P, ti, 0, r - rk, dex);
-                    w2 *= radial<double>(P, ti, 1, r - rk, dex);
-                }
-                z1 += fk * w1;
-                z2 += fk * w2;
+        const double r = sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
+        double z1 = 0, z2 = 0;
+        for (int e2 = 0; e2 < nb; e2++) {
+            if (e2 == e) continue;
+            const uint32_t ent2 = row[e2];
+            const double4 lk = xs[ent2 & J_MASK];
+            const int pk = ti * 2 + (int)lk.w;
+            const R3<double> dk = pair_vec<double>(li, lk, dtab[ent2 >> CODE_SHIFT]);
+            const double rk = sqrt(dk.x * dk.x + dk.y * dk.y + dk.z * dk.z);
+            const double cs = (d.x * dk.x + d.y * dk.y + d.z * dk.z) / (r * rk);
+            double dummy, dw, dex;
+            const double fk = cutoff<double>(rk, P.Rc[pk], P.Sc[pk], P.piSR[pk], dummy);
+            double w1 = angular<double>(P, ti, 0, cs, dw), w2 = angular<double>(P, ti, 1, cs, dw);
+            if (!P.alpha_zero[ti]) {
+                w1 *= radial<double>(P, ti, 0, r - rk, dex);
+                w2 *= radial<double>(P, ti, 1, r - rk, dex);
             }
-            double db1, db2, dfc;
-            const double b = bond_order<double>(P, ti, z1, z2, db1, db2);
-            const double fc = cutoff<double>(r, P.Rc[pp], P.Sc[pp], P.piSR[pp], dfc);
-            const double fR = P.A[pp] * exp(-P.lam1[pp] * r), fA = P.B[pp] * exp(-P.lam2[pp] * r);
-            ecov += 0.5 * fc * (fR - b * fA);
-            out.x = (R)b;
-            out.y = (R)(-0.5 * fc * fA * db1);
-            out.z = (R)(-0.5 * fc * fA * db2);
+            z1 += fk * w1;
+            z2 += fk * w2;
         }
+        double db1, db2, dfc;
+        const double b = bond_order<double>(P, ti, z1, z2, db1, db2);
+        const double fc = cutoff<double>(r, P.Rc[pp], P.Sc[pp], P.piSR[pp], dfc);
+        const double fR = P.A[pp] * exp(-P.lam1[pp] * r), fA = P.B[pp] * exp(-P.lam2[pp] * r);
+        ecov += 0.5 * fc * (fR - b * fA);
+        V4 out;
+        out.x = (R)b;
+        out.y = (R)(-0.5 * fc * fA * db1);
+        out.z = (R)(-0.5 * fc * fA * db2);
+        out.w = (R)0;
         slot[e] = out;
+        S.brev[rb + e] = S.cmap[(size_t)j * S.Ws + S.bsrev[rb + e]];
     }
     S.ecov[s] = ecov;
 }
@@ -237,32 +275,29 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
     const V4 *slot = reinterpret_cast<const V4 *>(S.slot);
     const V4 lm = xs[m];
     const int tm = (int)lm.w;
-    const int ns = S.scnt[m];
-    const uint32_t *row = S.sidx + (size_t)m * S.Ws;
+    const int nb = S.bcnt[m];
+    const size_t rb = (size_t)m * S.Ws;
+    const uint32_t *row = S.bidx + rb;
     double fx = 0, fy = 0, fz = 0;
     // m as the centre of its own bonds
-    for (int e = 0; e < ns; e++) {
+    for (int e = 0; e < nb; e++) {
         const uint32_t ent = row[e];
         const V4 lj = xs[ent & J_MASK];
         const int pp = tm * 2 + (int)lj.w;
         const R3<R> d = pair_vec<R>(lm, lj, dtab[ent >> CODE_SHIFT]);
-        const R r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-        if (r2 >= P.Sc[pp] * P.Sc[pp]) continue;
-        const R r = dev_sqrt(r2), ir = (R)1 / r;
-        const V4 sv = slot[(size_t)m * S.Ws + e];
+        const R r = dev_sqrt(d.x * d.x + d.y * d.y + d.z * d.z), ir = (R)1 / r;
+        const V4 sv = slot[rb + e];
         const R dv = pair_dvdr(P, pp, r, sv.x) * ir;
         R ax = dv * d.x, ay = dv * d.y, az = dv * d.z;
         if (sv.y != (R)0 || sv.z != (R)0) {
-            for (int e2 = 0; e2 < ns; e2++) {
+            for (int e2 = 0; e2 < nb; e2++) {
                 if (e2 == e) continue;
                 const uint32_t ent2 = row[e2];
                 const V4 lk = xs[ent2 & J_MASK];
                 const int pk = tm * 2 + (int)lk.w;
                 const R3<R> dk = pair_vec<R>(lm, lk, dtab[ent2 >> CODE_SHIFT]);
-                const R rk2 = dk.x * dk.x + dk.y * dk.y + dk.z * dk.z;
-                if (rk2 >= P.Sc[pk] * P.Sc[pk]) continue;
                 R3<R> gj[2], gk[2];
-                trip_grad(P, tm, pk, d, r, dk, dev_sqrt(rk2), gj, gk);
+                trip_grad(P, tm, pk, d, r, dk, dev_sqrt(dk.x * dk.x + dk.y * dk.y + dk.z * dk.z), gj, gk);
                 ax += sv.y * (gj[0].x + gk[0].x) + sv.z * (gj[1].x + gk[1].x);
                 ay += sv.y * (gj[0].y + gk[0].y) + sv.z * (gj[1].y + gk[1].y);
                 az += sv.z * (gj[1].z + gk[1].z) + sv.y * (gj[0].z + gk[0].z);
@@ -273,31 +308,29 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
         fz += (double)az;
     }
     // m as the partner j or the environment k of its neighbours' bonds
-    for (int e = 0; e < ns; e++) {
+    for (int e = 0; e < nb; e++) {
         const uint32_t ent = row[e];
         const int i = (int)(ent & J_MASK);
         const V4 li = xs[i];
         const int ti = (int)li.w, pp = ti * 2 + tm;
+        const int ni = S.bcnt[i];
+        const int rv = S.brev[rb + e];                        // bond (i -> m) in row i
+        if (rv >= ni) continue;                               // (a reverse always exists)
         const R3<R> dmi = pair_vec<R>(lm, li, dtab[ent >> CODE_SHIFT]);
-        const R r2 = dmi.x * dmi.x + dmi.y * dmi.y + dmi.z * dmi.z;
-        if (r2 >= P.Sc[pp] * P.Sc[pp]) continue;
-        const R r = dev_sqrt(r2), ir = (R)1 / r;
+        const R r = dev_sqrt(dmi.x * dmi.x + dmi.y * dmi.y + dmi.z * dmi.z), ir = (R)1 / r;
         const R3<R> d = {-dmi.x, -dmi.y, -dmi.z};            // i -> m
-        const int srev = S.srev[(size_t)m * S.Ws + e];
-        const V4 sv = slot[(size_t)i * S.Ws + srev];          // bond (i -> m)
+        const size_t ri = (size_t)i * S.Ws;
+        const V4 sv = slot[ri + rv];
         const R dv = pair_dvdr(P, pp, r, sv.x) * ir;
         R ax = -dv * d.x, ay = -dv * d.y, az = -dv * d.z;
-        const int ni = S.scnt[i];
-        const uint32_t *rowi = S.sidx + (size_t)i * S.Ws;
+        const uint32_t *rowi = S.bidx + ri;
         for (int t = 0; t < ni; t++) {
-            if (t == srev) continue;
+            if (t == rv) continue;
             const uint32_t ent2 = rowi[t];
             const V4 lk = xs[ent2 & J_MASK];
             const int pk = ti * 2 + (int)lk.w;
             const R3<R> dk = pair_vec<R>(li, lk, dtab[ent2 >> CODE_SHIFT]);   // i -> k
-            const R rk2 = dk.x * dk.x + dk.y * dk.y + dk.z * dk.z;
-            if (rk2 >= P.Sc[pk] * P.Sc[pk]) continue;
-            const R rk = dev_sqrt(rk2);
+            const R rk = dev_sqrt(dk.x * dk.x + dk.y * dk.y + dk.z * dk.z);
             R3<R> gj[2], gk[2];
             if (sv.y != (R)0 || sv.z != (R)0) {
                 // bond (i -> m), environment k: m is the partner j
@@ -306,7 +339,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
                 ay -= sv.y * gj[0].y + sv.z * gj[1].y;
                 az -= sv.y * gj[0].z + sv.z * gj[1].z;
             }
-            const V4 sk = slot[(size_t)i * S.Ws + t];             // bond (i -> k)
+            const V4 sk = slot[ri + t];                         // bond (i -> k)
             if (sk.y != (R)0 || sk.z != (R)0) {
                 // bond (i -> k), environment m: m is the environment atom
                 trip_grad(P, ti, pp, dk, rk, d, r, gj, gk);
