@@ -26,6 +26,7 @@ using namespace ctbop;
 namespace {
 
 constexpr int LPR = 16;             // lanes per Coulomb row (assembly, force gather)
+constexpr int BUILD_L = 8;          // lanes per atom in the list build (one cell's atoms at a time)
 constexpr int SPMV_U = 8;           // list entries in flight per row in the charge-solve product (tuned)
 
 thread_local std::string g_err;
@@ -423,7 +424,7 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
     hipLaunchKernelGGL(k_qfix, g, b, 0, st, P.dtiles, P.dseg);
     {
         Timed t(ctx, 7, st);
-        hipLaunchKernelGGL(k_build<R>, g, b, 0, st, P.dtiles, P.dseg, prm);
+        hipLaunchKernelGGL((k_build<R, BUILD_L>), g, b, 0, st, P.dtiles, P.dseg, prm);
     }
     hipLaunchKernelGGL(k_rev, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_mark_built, g1, dim3(64), 0, st, sid, P.dseg, 1);

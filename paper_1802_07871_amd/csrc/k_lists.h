@@ -266,69 +266,127 @@ __device__ __forceinline__ void load_dtab(const Seg &S, typename Vec4<R>::type *
 }
 
 // Both lists for every sorted atom: the cell stencil visited in a fixed order,
-// each cell's atoms in sorted order, so rows are deterministic.
-template <typename R>
-__global__ void k_build(const Tile *tiles, Seg *segs, Params<R> P)
+// each cell's atoms in sorted order, so rows are deterministic.  L lanes per
+// atom take L consecutive atoms of a cell at a time (one coalesced read of
+// their coordinates); group ballots place the accepted ones in list order.
+// Per-row statistics are reduced over the block before one atomic each.
+template <typename R, int L>
+__global__ void __launch_bounds__(TILE) k_build(const Tile *tiles, Seg *segs, Params<R> P)
 {
     using V4 = typename Vec4<R>::type;
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     if (!S.sst->rebuild) return;
     __shared__ V4 dtab[NCODE];
+    __shared__ int red[4][5];
     load_dtab<R>(S, dtab);
-    const int s = T.row0 + threadIdx.x;
-    if (s >= S.n) return;
     const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
-    const V4 li = xs[s];
-    const int ti = (int)li.w;
-    const int c = S.csort[s];
-    const int c0 = c / (S.nb[1] * S.nb[2]), c1 = (c / S.nb[2]) % S.nb[1], c2 = c % S.nb[2];
-    uint32_t *lrow = S.lidx + (size_t)s * S.Wl;
-    uint32_t *srow = S.sidx + (size_t)s * S.Ws;
-    int nl = 0, ns = 0, status = 0;
-    for (int d0 = -S.st[0]; d0 <= S.st[0]; d0++) {
-        int e0 = c0 + d0;
-        if (S.pbc[0]) { e0 %= S.nb[0]; if (e0 < 0) e0 += S.nb[0]; }
-        else if (e0 < 0 || e0 >= S.nb[0]) continue;
-        for (int d1 = -S.st[1]; d1 <= S.st[1]; d1++) {
-            int e1 = c1 + d1;
-            if (S.pbc[1]) { e1 %= S.nb[1]; if (e1 < 0) e1 += S.nb[1]; }
-            else if (e1 < 0 || e1 >= S.nb[1]) continue;
-            for (int d2 = -S.st[2]; d2 <= S.st[2]; d2++) {
-                int e2 = c2 + d2;
-                if (S.pbc[2]) { e2 %= S.nb[2]; if (e2 < 0) e2 += S.nb[2]; }
-                else if (e2 < 0 || e2 >= S.nb[2]) continue;
-                const int code = code_of(d0, d1, d2);
-                const V4 D = dtab[code];
-                const int cc = (e0 * S.nb[1] + e1) * S.nb[2] + e2;
-                const int m0 = S.cell_start[cc], m1 = S.cell_start[cc + 1];
-                for (int m = m0; m < m1; m++) {
-                    if (m == s && code == CODE_CENTER) continue;
-                    const V4 lj = xs[m];
-                    R rx = (lj.x - li.x) + D.x, ry = (lj.y - li.y) + D.y, rz = (lj.z - li.z) + D.z;
-                    float r2 = (float)(rx * rx + ry * ry + rz * rz);
-                    if (r2 >= P.l_cut2) continue;
-                    if (r2 < P.close2) status |= ST_TOO_CLOSE;
-                    const uint32_t ent = (uint32_t)m | ((uint32_t)code << CODE_SHIFT);
-                    if (nl < S.Wl) lrow[nl] = ent;
-                    nl++;
-                    const int tj = (int)lj.w;
-                    if (r2 < P.s_cut2[ti * 2 + tj]) {
-                        if (ns < S.Ws) srow[ns] = ent;
-                        ns++;
+    constexpr int G = TILE / L;
+    const int lane = threadIdx.x % L;
+    const unsigned below = (1u << lane) - 1u;
+    int st_or = 0, mx_l = 0, mx_s = 0, sum_l = 0, sum_s = 0;
+    for (int k = threadIdx.x / L; k < TILE; k += G) {
+        const int s = T.row0 + k;
+        if (s >= S.n) continue;                // the whole group skips together
+        const V4 li = xs[s];
+        const int ti = (int)li.w;
+        const int c = S.csort[s];
+        const int c0 = c / (S.nb[1] * S.nb[2]), c1 = (c / S.nb[2]) % S.nb[1], c2 = c % S.nb[2];
+        uint32_t *lrow = S.lidx + (size_t)s * S.Wl;
+        uint32_t *srow = S.sidx + (size_t)s * S.Ws;
+        int nl = 0, ns = 0;
+        bool close = false;
+        for (int d0 = -S.st[0]; d0 <= S.st[0]; d0++) {
+            int e0 = c0 + d0;
+            if (S.pbc[0]) { e0 %= S.nb[0]; if (e0 < 0) e0 += S.nb[0]; }
+            else if (e0 < 0 || e0 >= S.nb[0]) continue;
+            for (int d1 = -S.st[1]; d1 <= S.st[1]; d1++) {
+                int e1 = c1 + d1;
+                if (S.pbc[1]) { e1 %= S.nb[1]; if (e1 < 0) e1 += S.nb[1]; }
+                else if (e1 < 0 || e1 >= S.nb[1]) continue;
+                for (int d2 = -S.st[2]; d2 <= S.st[2]; d2++) {
+                    int e2 = c2 + d2;
+                    if (S.pbc[2]) { e2 %= S.nb[2]; if (e2 < 0) e2 += S.nb[2]; }
+                    else if (e2 < 0 || e2 >= S.nb[2]) continue;
+                    const int code = code_of(d0, d1, d2);
+                    const V4 D = dtab[code];
+                    const int cc = (e0 * S.nb[1] + e1) * S.nb[2] + e2;
+                    const int m0 = S.cell_start[cc], m1 = S.cell_start[cc + 1];
+                    for (int mb = m0; mb < m1; mb += L) {
+                        const int m = mb + lane;
+                        bool inl = false, ins = false;
+                        uint32_t ent = 0;
+                        if (m < m1 && !(m == s && code == CODE_CENTER)) {
+                            const V4 lj = xs[m];
+                            R rx = (lj.x - li.x) + D.x, ry = (lj.y - li.y) + D.y, rz = (lj.z - li.z) + D.z;
+                            float r2 = (float)(rx * rx + ry * ry + rz * rz);
+                            if (r2 < P.l_cut2) {
+                                inl = true;
+                                if (r2 < P.close2) close = true;
+                                ins = r2 < P.s_cut2[ti * 2 + (int)lj.w];
+                                ent = (uint32_t)m | ((uint32_t)code << CODE_SHIFT);
+                            }
+                        }
+                        const unsigned gl = group_ballot<L>(inl), gs = group_ballot<L>(ins);
+                        if (inl) {
+                            const int at = nl + __popc(gl & below);
+                            if (at < S.Wl) lrow[at] = ent;
+                        }
+                        if (ins) {
+                            const int at = ns + __popc(gs & below);
+                            if (at < S.Ws) srow[at] = ent;
+                        }
+                        nl += __popc(gl);
+                        ns += __popc(gs);
                     }
                 }
             }
         }
+        const bool any_close = group_ballot<L>(close) != 0u;
+        if (lane == 0) {
+            if (any_close) st_or |= ST_TOO_CLOSE;
+            if (nl > S.Wl || ns > S.Ws) st_or |= ST_OVERFLOW;
+            const int cl = nl < S.Wl ? nl : S.Wl, cs = ns < S.Ws ? ns : S.Ws;
+            S.lcnt[s] = cl;
+            S.scnt[s] = cs;
+            mx_l = max(mx_l, nl);
+            mx_s = max(mx_s, ns);
+            sum_l += cl;
+            sum_s += cs;
+        }
     }
-    if (nl > S.Wl || ns > S.Ws) status |= ST_OVERFLOW;
-    S.lcnt[s] = nl < S.Wl ? nl : S.Wl;
-    S.scnt[s] = ns < S.Ws ? ns : S.Ws;
-    atomicMax(&S.sst->maxl, nl);
-    atomicMax(&S.sst->maxs, ns);
-    atomicAdd(&S.sst->nnz_long, (unsigned long long)S.lcnt[s]);
-    atomicAdd(&S.sst->nnz_short, (unsigned long long)S.scnt[s]);
-    if (status) atomicOr(&S.sst->status, status);
+    // block totals, then one atomic per statistic
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        st_or |= __shfl_xor(st_or, o, 64);
+        mx_l = max(mx_l, __shfl_xor(mx_l, o, 64));
+        mx_s = max(mx_s, __shfl_xor(mx_s, o, 64));
+        sum_l += __shfl_xor(sum_l, o, 64);
+        sum_s += __shfl_xor(sum_s, o, 64);
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[wv][0] = st_or;
+        red[wv][1] = mx_l;
+        red[wv][2] = mx_s;
+        red[wv][3] = sum_l;
+        red[wv][4] = sum_s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; w++) {
+            red[0][0] |= red[w][0];
+            red[0][1] = max(red[0][1], red[w][1]);
+            red[0][2] = max(red[0][2], red[w][2]);
+            red[0][3] += red[w][3];
+            red[0][4] += red[w][4];
+        }
+        if (red[0][0]) atomicOr(&S.sst->status, red[0][0]);
+        atomicMax(&S.sst->maxl, red[0][1]);
+        atomicMax(&S.sst->maxs, red[0][2]);
+        atomicAdd(&S.sst->nnz_long, (unsigned long long)red[0][3]);
+        atomicAdd(&S.sst->nnz_short, (unsigned long long)red[0][4]);
+    }
 }
 
 // For every covalent entry (i -> j, d) the slot of (j -> i, -d) in row j.

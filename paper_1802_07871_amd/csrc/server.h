@@ -292,7 +292,7 @@ int server_tick(ctbop_server *S, const Params<R> &prm)
         hipLaunchKernelGGL(k_gather<R>, g, b, 0, st, T, S->dsegs, -1);
         hipLaunchKernelGGL(k_fin_qshift, gs, b, 0, st, sid, S->dsegs);
         hipLaunchKernelGGL(k_qfix, g, b, 0, st, T, S->dsegs);
-        hipLaunchKernelGGL(k_build<R>, g, b, 0, st, T, S->dsegs, prm);
+        hipLaunchKernelGGL((k_build<R, BUILD_L>), g, b, 0, st, T, S->dsegs, prm);
         hipLaunchKernelGGL(k_rev, g, b, 0, st, T, S->dsegs);
         hipLaunchKernelGGL(k_mark_built, dim3((nis + 63) / 64), dim3(64), 0, st, sid, S->dsegs, nis);
         hipLaunchKernelGGL(k_bcompact, g, b, 0, st, T, S->dsegs, ctx->pd);
