@@ -88,9 +88,10 @@ extern "C" {
 /* flags of ctbop_compute_energy_forces_charges */
 #define CTBOP_FLAG_WARM_START    1  /* start the charge solve from the last call's charges */
 #define CTBOP_FLAG_FORCE_REBUILD 2  /* rebuild cell bins and lists regardless of motion   */
-#define CTBOP_FLAG_EXTRAPOLATE   4  /* with WARM_START: start from the quadratic (or linear)
-                                       extrapolation of the last three (two) solutions, for
-                                       consecutive MD steps; ctbop_md_run always does this  */
+#define CTBOP_FLAG_EXTRAPOLATE   4  /* with WARM_START: start from the polynomial extrapolation
+                                       of the last four (three, two) solutions, cubic
+                                       (quadratic, linear), for consecutive MD steps;
+                                       ctbop_md_run always does this                        */
 
 typedef struct ctbop_ctx ctbop_ctx;
 

@@ -220,9 +220,10 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
     size_t o_bcnt = take(4 * np), o_bidx = take(4 * np * S.Ws), o_cmap = take(np * S.Ws), o_bsrev = take(np * S.Ws),
            o_brev = take(np * S.Ws);
     size_t o_ecov = take(8 * np), o_fcov = take(8 * 3 * np);
-    size_t o_q = take(8 * np), o_r = take(8 * np), o_p = take(8 * np), o_s = take(8 * np), o_d = take(8 * np),
-           o_jd = take(8 * np);
-    size_t o_qs = take(8 * (size_t)n), o_qh1 = take(8 * (size_t)n), o_qh2 = take(8 * (size_t)n);
+    size_t o_q = take(8 * np), o_r = take(8 * np), o_p = take(8 * np), o_s = take(8 * np), o_jd = take(8 * np);
+    size_t o_binv = take(8 * np * BK), o_m1 = take(8 * np), o_y = take(8 * np);
+    size_t o_qs = take(8 * (size_t)n), o_qh1 = take(8 * (size_t)n), o_qh2 = take(8 * (size_t)n),
+           o_qh3 = take(8 * (size_t)n);
     size_t o_part = take(8 * NPART * (size_t)S.ntile);
     L.bytes = o;
     L.ntile = S.ntile;
@@ -258,11 +259,14 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
         S.r = (double *)(base + o_r);
         S.p = (double *)(base + o_p);
         S.s = (double *)(base + o_s);
-        S.dinv = (double *)(base + o_d);
+        S.binv = (double *)(base + o_binv);
+        S.m1 = (double *)(base + o_m1);
+        S.y = (double *)(base + o_y);
         S.jd = (double *)(base + o_jd);
         S.q_state = (double *)(base + o_qs);
         S.q_h1 = (double *)(base + o_qh1);
         S.q_h2 = (double *)(base + o_qh2);
+        S.q_h3 = (double *)(base + o_qh3);
         S.part = (double *)(base + o_part);
         S.sst = (SegState *)(base + L.off_sst);
     }

@@ -22,6 +22,7 @@ constexpr int NCODE = 343;             // offsets (-3..3)^3
 constexpr int CODE_CENTER = 171;       // offset (0,0,0)
 constexpr int MAX_ATOMS = (1 << CODE_SHIFT) - 1;
 constexpr int SLICE = 64;              // rows per slice of the sliced list layout (one wave)
+constexpr int BK = 16;                 // rows per block of the block-Jacobi preconditioner
 
 // status bits (mapped to CTBOP_E_* codes on the host)
 constexpr int ST_TOO_CLOSE = 1, ST_NOCONV = 2, ST_NOT_PD = 4, ST_OVERFLOW = 8, ST_REV = 16;
@@ -58,13 +59,13 @@ struct SegState {
     int status;        // ST_* bits, sticky until the next rebuild/call reset
     int maxl, maxs;    // largest list rows at the last build
     int built;         // lists exist
-    int nhist;         // charge solutions kept for the starting-charge predictor (0..3)
+    int nhist;         // charge solutions kept for the starting-charge predictor (0..4)
     int warm;          // per-segment start mode when a launch passes warm < 0 (serving)
     int forces_done;   // serving: forces and energy of the current request are written
     int nrebuild;      // rebuilds since the system buffer was set up
     double w;          // current residual shift
     double rho, alpha, beta, res;
-    double sdinv;      // sum of 1/diag
+    double sdinv;      // 1^T M 1 (sum of the preconditioner's row sums)
     double mu_prev;    // chemical potential of the previous solve
     double mshift;     // accumulated shift: r_stored = -(Hq+chi) + mshift
     double qshift;     // final re-projection of q onto sum q = Q
@@ -136,9 +137,14 @@ struct Seg {
     void *slot;        // [npad * Ws] per bond, float4 / double4: b, P1, P2, -
     double *ecov;      // [npad]
     double *Fcov;      // SoA [3 npad]
-    double *q, *r, *p, *s, *dinv, *jd;   // [npad]
+    double *q, *r, *p, *s, *jd;          // [npad]
+    // block-Jacobi preconditioner: the inverse of each diagonal BK x BK block
+    // of H (blocks of BK consecutive sorted rows, symmetric; entry (t, u) of
+    // block b at b*BK*BK + t*BK + u), its row sums m1 = B^-1 1, and y = B^-1 r
+    double *binv;      // [npad * BK]
+    double *m1, *y;    // [npad]
     double *q_state;   // user order charges of the last solve, for the warm start [n]
-    double *q_h1, *q_h2;   // the two solves before it (predictor history) [n]
+    double *q_h1, *q_h2, *q_h3;   // the three solves before it (predictor history) [n]
     double *part;      // [ntile * NPART]
     SegState *sst;
 };

@@ -109,8 +109,8 @@ __global__ void __launch_bounds__(TILE) k_adj_init(const Tile *tiles, Seg *segs,
         S.q[s] = 0.0;          // the adjoint view's q is lambda
         S.r[s] = r;
         S.p[s] = 0.0;
-        v[0] = r * S.dinv[s];
-        v[4] = S.dinv[s];
+        v[0] = r * S.m1[s];
+        v[4] = S.m1[s];
     } else if (s < S.npad) {
         S.q[s] = 0.0;
     }

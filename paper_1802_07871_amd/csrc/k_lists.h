@@ -192,7 +192,8 @@ __global__ void k_cell_sort(const Tile *tiles, Seg *segs)
 // Local coordinates of every sorted atom for this call's positions, and the
 // starting charges in the sorted frame (with their sum, for the projection).
 // warm: 0 = zeros, 1 = the last solution, 2 = extrapolate the last solutions
-// (quadratic through three, linear through two), for consecutive MD steps.
+// by the polynomial through as many as are kept (cubic through four, else
+// quadratic through three, linear through two), for consecutive MD steps.
 template <typename R>
 __global__ void k_gather(const Tile *tiles, Seg *segs, int warm)
 {
@@ -218,7 +219,8 @@ __global__ void k_gather(const Tile *tiles, Seg *segs, int warm)
         const int wm = warm < 0 ? S.sst->warm : warm;
         if (wm) {
             const int nh = wm == 2 ? S.sst->nhist : 1;
-            if (nh >= 3) q0 = 3.0 * S.q_state[i] - 3.0 * S.q_h1[i] + S.q_h2[i];
+            if (nh >= 4) q0 = 4.0 * S.q_state[i] - 6.0 * S.q_h1[i] + 4.0 * S.q_h2[i] - S.q_h3[i];
+            else if (nh == 3) q0 = 3.0 * S.q_state[i] - 3.0 * S.q_h1[i] + S.q_h2[i];
             else if (nh == 2) q0 = 2.0 * S.q_state[i] - S.q_h1[i];
             else if (nh == 1) q0 = S.q_state[i];
         }

@@ -4,9 +4,11 @@
 // self energy chi q + J q^2/2 and the Coulomb kernel C_ij, the energy is
 // quadratic in q, so the minimiser solves  H q + chi = mu 1,  sum q = Q,
 // H = diag(J) + [C_ij summed over images].  It is found by projected
-// Jacobi-preconditioned conjugate gradients:
-//   z = D^-1 (r - w 1),  w = (1^T D^-1 r) / (1^T D^-1 1),
-// which keeps every direction on sum z = 0.  The residual r is stored shifted
+// block-Jacobi-preconditioned conjugate gradients:
+//   z = M (r - w 1),  w = (1^T M r) / (1^T M 1),
+// which keeps every direction on sum z = 0; M is the inverse of the diagonal
+// blocks of H over BK consecutive sorted rows (atoms of one or two cells,
+// which carry the strongest couplings).  The residual r is stored shifted
 // by the running w (r = -(Hq + chi) + const), so it never carries the large
 // multiplier mu, whose rounding would otherwise swamp r^T z.  Vectors,
 // dot products and the projection are FP64; the matrix entries are stored in
@@ -71,8 +73,8 @@ __device__ __forceinline__ double entry_r(const typename Vec4<R>::type &li, cons
 }
 
 // Assemble the Coulomb rows of the step: the list entries inside rc, in list
-// order, into hidx/Hr (group ballots give each lane its slot), the diagonal
-// (J plus self images) and the starting residual r = -(H q0 + chi) + mu_prev.
+// order, into hidx/Hr (group ballots give each lane its slot), and the
+// starting residual r = -(H q0 + chi) + mu_prev.
 template <typename R, int LPR>
 __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs, Params<double> PD)
 {
@@ -80,7 +82,6 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     __shared__ V4 dtab[NCODE];
-    __shared__ double lds[4 * 5];
     load_dtab2<R>(S, dtab);
     const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
     R *Hr = reinterpret_cast<R *>(S.Hr);
@@ -88,7 +89,6 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
     constexpr int G = TILE / LPR;
     const int lane = threadIdx.x % LPR;
     const unsigned below = (1u << lane) - 1u;
-    double acc5[5] = {0, 0, 0, 0, 0};
     for (int k = threadIdx.x / LPR; k < TILE; k += G) {
         const int s = T.row0 + k;
         if (s >= S.n) {
@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
         const uint32_t *row = S.lidx + (size_t)s * S.Wl;
         uint32_t *hrow = S.hidx + (size_t)s * S.Wl;
         R *vrow = Hr + (size_t)s * S.Wl;
-        double acc = 0.0, self = 0.0;
+        double acc = 0.0;
         int pos = 0;
         for (int e0 = 0; e0 < cnt; e0 += LPR) {
             const int e = e0 + lane;
@@ -125,45 +125,47 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
                 hrow[at] = ent;
                 vrow[at] = c;
                 acc += (double)c * S.q[j];
-                if (j == s) self += (double)c;
             }
             pos += __popc(gm);
         }
         acc = group_sum<LPR>(acc);
-        self = group_sum<LPR>(self);
         if (lane == 0) {
             const double qs = S.q[s];
-            const double di = 1.0 / (PD.J[ti] + self);
-            const double r = -(PD.J[ti] * qs + acc + PD.chi[ti]) + mprev;
             S.hcnt[s] = pos;
-            S.dinv[s] = di;
             S.jd[s] = PD.J[ti];
-            S.r[s] = r;
+            S.r[s] = -(PD.J[ti] * qs + acc + PD.chi[ti]) + mprev;
             S.p[s] = 0.0;
-            acc5[0] += r * di;
-            acc5[1] += (double)pos;
-            acc5[4] += di;
         }
     }
-    tile_partials<5>(S, T.row0 / TILE, acc5, lds);
 }
 
 // Sliced copy (hsidx, H) of the step's rows (hidx, Hr) for the charge-solve
-// product.  Each block transposes its tile through LDS in chunks of HS_CH
-// entries: HS_CH lanes read a row segment, then each lane writes its row's
-// chunk as slice columns; both sides touch contiguous memory.
+// product, and the block-Jacobi preconditioner.  Each block transposes its
+// tile through LDS in chunks of HS_CH entries: HS_CH lanes read a row
+// segment, then each lane writes its row's chunk as slice columns (both sides
+// touch contiguous memory) and adds the entries whose neighbour lies in its
+// own BK-row block to that block row, in list order.  The tile's blocks (J on
+// the diagonal) are then inverted in LDS by Gauss-Jordan elimination (H is
+// SPD, so no pivoting), symmetrised and written with their row sums; the
+// tile's partial sums of r m1 and m1 start the projection.
 constexpr int HS_CH = 16;
 template <typename R>
 __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
 {
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
-    __shared__ uint32_t ci[TILE][HS_CH + 1];
-    __shared__ R cv[TILE][HS_CH + 1];
+    constexpr int CI_BYTES = TILE * (HS_CH + 1) * 4, CV_BYTES = TILE * (HS_CH + 1) * (int)sizeof(R);
+    constexpr int HB_BYTES = (TILE / BK) * BK * (BK + 1) * 8;
+    constexpr int BUF = (CI_BYTES + CV_BYTES > HB_BYTES) ? CI_BYTES + CV_BYTES : HB_BYTES;
+    __shared__ __align__(16) unsigned char buf[BUF];
     __shared__ int cnt_lds[TILE];
     __shared__ int mx[4];
+    __shared__ double lds[4 * 5];
+    uint32_t(*ci)[HS_CH + 1] = reinterpret_cast<uint32_t(*)[HS_CH + 1]>(buf);
+    R(*cv)[HS_CH + 1] = reinterpret_cast<R(*)[HS_CH + 1]>(buf + CI_BYTES);
     const int own = T.row0 + threadIdx.x;
-    const int own_cnt = own < S.n ? S.hcnt[own] : 0;
+    const bool live = own < S.n;
+    const int own_cnt = live ? S.hcnt[own] : 0;
     cnt_lds[threadIdx.x] = own_cnt;
     int m = own_cnt;
 #pragma unroll
@@ -175,6 +177,10 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
     R *H = reinterpret_cast<R *>(S.H);
     const int lane = threadIdx.x % HS_CH;
     const size_t b0 = slice_base(own, S.Wl);
+    const int bbase = own & ~(BK - 1);
+    double hb[BK];
+#pragma unroll
+    for (int t = 0; t < BK; t++) hb[t] = 0.0;
     for (int E0 = 0; E0 < maxc; E0 += HS_CH) {
         for (int k = threadIdx.x / HS_CH; k < TILE; k += TILE / HS_CH) {
             const int e = E0 + lane;
@@ -187,14 +193,76 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
         __syncthreads();
         const int lim = min(HS_CH, own_cnt - E0);
         for (int e = 0; e < lim; e++) {
-            S.hsidx[b0 + (size_t)(E0 + e) * SLICE] = ci[threadIdx.x][e];
-            H[b0 + (size_t)(E0 + e) * SLICE] = cv[threadIdx.x][e];
+            const uint32_t ent = ci[threadIdx.x][e];
+            const R v = cv[threadIdx.x][e];
+            S.hsidx[b0 + (size_t)(E0 + e) * SLICE] = ent;
+            H[b0 + (size_t)(E0 + e) * SLICE] = v;
+            const unsigned col = (unsigned)((int)(ent & J_MASK) - bbase);
+            if (col < (unsigned)BK) {
+#pragma unroll
+                for (int t = 0; t < BK; t++) hb[t] += (col == (unsigned)t) ? (double)v : 0.0;
+            }
         }
         __syncthreads();
     }
+    // the tile's BK x BK blocks, one row per thread ([block][row][col])
+    double(*A)[BK][BK + 1] = reinterpret_cast<double(*)[BK][BK + 1]>(buf);
+    const int blk = threadIdx.x / BK, i = threadIdx.x % BK;
+#pragma unroll
+    for (int t = 0; t < BK; t++) A[blk][i][t] = live ? hb[t] : (t == i ? 1.0 : 0.0);
+    if (live) A[blk][i][i] += S.jd[own];
+    __syncthreads();
+    // in-place Gauss-Jordan inversion, thread i updates row i
+    for (int k = 0; k < BK; k++) {
+        const double piv = 1.0 / A[blk][k][k];
+        const double aik = A[blk][i][k];
+        double rowk[BK];
+#pragma unroll
+        for (int t = 0; t < BK; t++) rowk[t] = A[blk][k][t];
+        __syncthreads();
+        if (i == k) {
+#pragma unroll
+            for (int t = 0; t < BK; t++) A[blk][k][t] = (t == k) ? piv : rowk[t] * piv;
+        } else {
+            const double f = aik * piv;
+#pragma unroll
+            for (int t = 0; t < BK; t++) A[blk][i][t] = (t == k) ? -f : A[blk][i][t] - f * rowk[t];
+        }
+        __syncthreads();
+    }
+    double m1 = 0.0;
+    double *bo = S.binv + (size_t)(T.row0 + blk * BK) * BK;
+#pragma unroll
+    for (int t = 0; t < BK; t++) {
+        const double b = 0.5 * (A[blk][i][t] + A[blk][t][i]);
+        bo[t * BK + i] = b;
+        m1 += b;
+    }
+    double v[5] = {0, 0, 0, 0, 0};
+    if (live) {
+        S.m1[own] = m1;
+        v[0] = S.r[own] * m1;
+        v[1] = (double)own_cnt;
+        v[4] = m1;
+    } else if (own < S.npad) {
+        S.m1[own] = 0.0;
+    }
+    tile_partials<5>(S, T.row0 / TILE, v, lds);
 }
 
-// First pass over the starting residual: its D-weighted mean w0.
+// y = M r for row s: the row of s's block inverse against the block's r,
+// exchanged by shuffles within the BK lanes of the block (every lane of the
+// block must call it; rows past n pass r = 0).
+__device__ __forceinline__ double block_apply(const Seg &S, int s, double r)
+{
+    const double *B = S.binv + (size_t)(s & ~(BK - 1)) * BK + (s & (BK - 1));
+    double y = 0.0;
+#pragma unroll
+    for (int t = 0; t < BK; t++) y += B[t * BK] * __shfl(r, t, BK);
+    return y;
+}
+
+// First pass over the starting residual: its M-weighted mean w0 = 1^T M r / 1^T M 1.
 __global__ void k_fin_w0(const int *seg_ids, Seg *segs)
 {
     const Seg &S = segs[seg_ids[blockIdx.x]];
@@ -219,13 +287,18 @@ __global__ void __launch_bounds__(TILE) k_shift_stats(const Tile *tiles, Seg *se
     const Seg &S = segs[T.seg];
     __shared__ double lds[4 * 4];
     const int s = T.row0 + threadIdx.x;
-    double v[4] = {0, 0, 0, 0};
-    if (s < S.n) {
-        const double r = S.r[s] - S.sst->w;
-        const double di = S.dinv[s];
+    const bool live = s < S.n;
+    double r = 0.0;
+    if (live) {
+        r = S.r[s] - S.sst->w;
         S.r[s] = r;
-        v[0] = r * di;
-        v[1] = r * r * di;
+    }
+    const double y = block_apply(S, s, r);
+    double v[4] = {0, 0, 0, 0};
+    if (live) {
+        S.y[s] = y;
+        v[0] = r * S.m1[s];
+        v[1] = r * y;
         v[2] = r;
         v[3] = r * r;
     }
@@ -255,7 +328,7 @@ __global__ void k_fin_assemble(const int *seg_ids, Seg *segs, CgCtl ctl)
     }
 }
 
-// r <- r - w,  p <- D^-1 r + beta p
+// r <- r - w,  p <- M (r - w 1) + beta p = (y - w m1) + beta p
 __global__ void __launch_bounds__(TILE) k_cg_dir(const Tile *tiles, Seg *segs)
 {
     const Tile T = my_tile(tiles);
@@ -266,7 +339,7 @@ __global__ void __launch_bounds__(TILE) k_cg_dir(const Tile *tiles, Seg *segs)
     const double w = S.sst->w, beta = S.sst->beta;
     const double r = S.r[s] - w;
     S.r[s] = r;
-    S.p[s] = S.dinv[s] * r + beta * S.p[s];
+    S.p[s] = (S.y[s] - w * S.m1[s]) + beta * S.p[s];
 }
 
 // s = H p and the tile's share of p^T s, one row per lane; U entries of the
@@ -335,7 +408,7 @@ __global__ void k_fin_alpha(const int *seg_ids, Seg *segs)
     }
 }
 
-// q += alpha p, r -= alpha s, and the tile's sums for w, rho and the test
+// q += alpha p, r -= alpha s, y = M r, and the tile's sums for w, rho and the test
 __global__ void __launch_bounds__(TILE) k_cg_update(const Tile *tiles, Seg *segs)
 {
     const Tile T = my_tile(tiles);
@@ -343,16 +416,21 @@ __global__ void __launch_bounds__(TILE) k_cg_update(const Tile *tiles, Seg *segs
     if (S.sst->done) return;
     __shared__ double lds[4 * 5];
     const int s = T.row0 + threadIdx.x;
+    const bool live = s < S.n;
     const double alpha = S.sst->alpha;
-    double v[5] = {0, 0, 0, 0, 0};
-    if (s < S.n) {
-        const double q = S.q[s] + alpha * S.p[s];
-        const double r = S.r[s] - alpha * S.s[s];
-        const double di = S.dinv[s];
+    double q = 0.0, r = 0.0;
+    if (live) {
+        q = S.q[s] + alpha * S.p[s];
+        r = S.r[s] - alpha * S.s[s];
         S.q[s] = q;
         S.r[s] = r;
-        v[0] = r * di;
-        v[1] = r * r * di;
+    }
+    const double y = block_apply(S, s, r);
+    double v[5] = {0, 0, 0, 0, 0};
+    if (live) {
+        S.y[s] = y;
+        v[0] = r * S.m1[s];
+        v[1] = r * y;
         v[2] = r;
         v[3] = r * r;
         v[4] = q;
@@ -442,6 +520,7 @@ __global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *seg
             S.F[2 * S.n + i] = qs * fz + S.Fcov[2 * S.npad + s];
             S.q_out[i] = qs;
             if (keep_hist) {
+                S.q_h3[i] = S.q_h2[i];
                 S.q_h2[i] = S.q_h1[i];
                 S.q_h1[i] = S.q_state[i];
             }
@@ -465,7 +544,7 @@ __global__ void k_fin_energy(const int *seg_ids, Seg *segs, int gate)
         st->energy = tot[0];
         if (S.E_out) *S.E_out = tot[0];
         st->mu_prev = st->mshift;
-        st->nhist = st->nhist < 3 ? st->nhist + 1 : 3;
+        st->nhist = st->nhist < 4 ? st->nhist + 1 : 4;
         st->forces_done = 1;
     }
 }
