@@ -333,7 +333,7 @@ def main():
     ap.add_argument("--fp64", action="store_true", help="FP64 pair terms (default: FP32 terms, FP64 sums)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-nx", type=int, default=40)
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--serving", action="store_true",
                     help="serving benchmark only: 4096 Poisson requests at 5 loads vs per-request launches")
     ap.add_argument("--serve-requests", type=int, default=None)
