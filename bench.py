@@ -428,14 +428,17 @@ def main():
     # convergence exit at once, so the average is taken over the iterations
     # that ran (a slight overestimate of the per-launch time).
     nnz = int(info["nnz_coul"])               # entries inside rc (the assembled rows)
+    nnz_wide = int(info["nnz_coul_wide"])     # of which with full indices in the sliced copy
     ms, cnt = prof["spmv"]
     iters = int(info["cg_iters_total"]) - int(info_w["cg_iters_total"])
     avg_s = ms / 1e3 / max(iters, 1)
-    spmv_bytes = 8.0 * nnz + 32.0 * n          # entry (index + value) + row offset, count, p, diagonal, result
+    # entry: FP32 value + 16-bit row offset (32-bit index in wide slices);
+    # row: count, p_i, J_i, result s_i
+    spmv_bytes = 6.0 * nnz + 2.0 * nnz_wide + 28.0 * n
     achieved = spmv_bytes / avg_s / 1e9
     fms, fcnt = prof["force_coul"]
     f_avg = fms / 1e3 / max(fcnt, 1)
-    force_bytes = 4.0 * nnz + 80.0 * n         # entry index + per-row offset, count, positions, charges, forces
+    force_bytes = 4.0 * nnz + 80.0 * n         # entry index + per-row count, positions, charges, forces
     kernels = {k: {"avg_us": (m / max(c, 1)) * 1e3, "launches": c, "total_ms": m} for k, (m, c) in prof.items()}
 
     out = {
@@ -454,7 +457,7 @@ def main():
         "config": {
             "workload": f"4H-SiC(0001) Si-face stepped slab {args.nx}x{args.nx} cells x {args.nbil} bilayers, "
                         f"30% top-Si depleted, {n} atoms, 2500 K NVE, dt 0.5 fs, charges to 1e-9 every step",
-            "n_atoms": n, "cg_iters_last_step": info["cg_iters"], "nnz_coulomb": nnz,
+            "n_atoms": n, "cg_iters_last_step": info["cg_iters"], "nnz_coulomb": nnz, "nnz_coulomb_wide": nnz_wide,
             "nnz_long_list": int(info["nnz_long"]),
             "nnz_short": int(info["nnz_short"]),
             "cg_iters_per_step": iters / args.steps, "list_rebuilds": int(info["n_rebuild"]) - int(info_w["n_rebuild"]),

@@ -120,6 +120,8 @@ typedef struct {
     unsigned long long cg_iters_total;  /* charge-solve iterations since set-up */
     double cg_res0;     /* starting RMS projected residual of the last solve   */
     unsigned long long nnz_coul;  /* Coulomb entries inside rc at the last assembly */
+    unsigned long long nnz_coul_wide; /* of which stored with full (32-bit) indices in the
+                                         solver's sliced copy (the rest: 16-bit offsets) */
 } ctbop_info;
 
 /* Fill *o with the defaults above. */

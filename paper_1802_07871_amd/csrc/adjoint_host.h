@@ -76,7 +76,7 @@ AdjLayout adj_layout(const Layout &L)
     A.off_v = take(8 * 3 * np);
     A.off_a = take(8 * np);
     A.off_lam = take(8 * np);
-    A.off_slot = take(8 * 6 * np * (size_t)L.seg.Ws);
+    A.off_slot = take(8 * 6 * np * (size_t)L.seg.Wb);
     A.off_scal = take(8 * 8);
     A.off_grad = take(8 * 64);
     A.off_seg = take(sizeof(Seg));

@@ -194,6 +194,7 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
     S.tile0 = 0;
     S.Wl = ctx->opts.long_cap;
     S.Ws = ctx->opts.short_cap;
+    S.Wb = std::min(S.Ws, WB);
     S.skin = ctx->opts.skin;
     const int fp64 = ctx->opts.fp64;
     const size_t rsz = fp64 ? 8 : 4, v4 = fp64 ? 32 : 16;
@@ -215,10 +216,10 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
     size_t o_xs64 = fp64 ? o_xs : take(32 * np);
     size_t o_lcnt = take(4 * np), o_lidx = take(4 * np * S.Wl), o_H = take(rsz * np * S.Wl);
     size_t o_hcnt = take(4 * np), o_hidx = take(4 * np * S.Wl), o_Hr = take(rsz * np * S.Wl);
-    size_t o_hsidx = take(4 * np * S.Wl);
-    size_t o_scnt = take(4 * np), o_sidx = take(4 * np * S.Ws), o_srev = take(np * S.Ws), o_slot = take(v4 * np * S.Ws);
-    size_t o_bcnt = take(4 * np), o_bidx = take(4 * np * S.Ws), o_cmap = take(np * S.Ws), o_bsrev = take(np * S.Ws),
-           o_brev = take(np * S.Ws);
+    size_t o_hsidx = take(4 * np * S.Wl), o_hs16 = take(2 * np * S.Wl), o_hwide = take(np), o_swide = take(np / SLICE);
+    size_t o_scnt = take(4 * np), o_sidx = take(4 * np * S.Ws), o_srev = take(np * S.Ws);
+    size_t o_bcnt = take(4 * np), o_bidx = take(4 * np * S.Wb), o_bsrev = take(np * S.Wb), o_cmap = take(np * S.Ws),
+           o_slot = take(v4 * np * S.Wb);
     size_t o_ecov = take(8 * np), o_fcov = take(8 * 3 * np);
     size_t o_q = take(8 * np), o_r = take(8 * np), o_p = take(8 * np), o_s = take(8 * np), o_jd = take(8 * np);
     size_t o_binv = take(8 * np * BK), o_m1 = take(8 * np), o_y = take(8 * np);
@@ -244,14 +245,16 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
         S.hidx = (uint32_t *)(base + o_hidx);
         S.Hr = base + o_Hr;
         S.hsidx = (uint32_t *)(base + o_hsidx);
+        S.hs16 = (uint16_t *)(base + o_hs16);
+        S.hwide = (uint8_t *)(base + o_hwide);
+        S.swide = (uint8_t *)(base + o_swide);
         S.scnt = (int *)(base + o_scnt);
         S.sidx = (uint32_t *)(base + o_sidx);
         S.srev = (uint8_t *)(base + o_srev);
         S.bcnt = (int *)(base + o_bcnt);
         S.bidx = (uint32_t *)(base + o_bidx);
-        S.cmap = (uint8_t *)(base + o_cmap);
         S.bsrev = (uint8_t *)(base + o_bsrev);
-        S.brev = (uint8_t *)(base + o_brev);
+        S.cmap = (uint8_t *)(base + o_cmap);
         S.slot = base + o_slot;
         S.ecov = (double *)(base + o_ecov);
         S.Fcov = (double *)(base + o_fcov);
@@ -432,7 +435,6 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
     }
     hipLaunchKernelGGL(k_rev, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_mark_built, g1, dim3(64), 0, st, sid, P.dseg, 1);
-    hipLaunchKernelGGL(k_bcompact, g, b, 0, st, P.dtiles, P.dseg, ctx->pd);
     {
         Timed t(ctx, 3, st);
         hipLaunchKernelGGL((k_bond<R>), g, b, 0, st, P.dtiles, P.dseg, ctx->pd);
@@ -534,6 +536,7 @@ int fill_info(ctbop_ctx *ctx, Prep &P, ctbop_info *info)
     info->cg_iters_total = ss.iters_total;
     info->cg_res0 = ss.res0;
     info->nnz_coul = (unsigned long long)ss.nnz_coul;
+    info->nnz_coul_wide = (unsigned long long)ss.nnz_wide;
     if (ss.status) return fail(info->status, status_text(ss.status));
     return CTBOP_OK;
 }

@@ -23,6 +23,7 @@ constexpr int CODE_CENTER = 171;       // offset (0,0,0)
 constexpr int MAX_ATOMS = (1 << CODE_SHIFT) - 1;
 constexpr int SLICE = 64;              // rows per slice of the sliced list layout (one wave)
 constexpr int BK = 16;                 // rows per block of the block-Jacobi preconditioner
+constexpr int WB = 32;                 // bond-row capacity (bonds inside S_ij per atom)
 
 // status bits (mapped to CTBOP_E_* codes on the host)
 constexpr int ST_TOO_CLOSE = 1, ST_NOCONV = 2, ST_NOT_PD = 4, ST_OVERFLOW = 8, ST_REV = 16;
@@ -74,6 +75,7 @@ struct SegState {
     unsigned long long iters_total;           // charge-solve iterations since set-up
     double res0;                              // starting residual of the last solve
     double nnz_coul;                          // Coulomb entries inside rc at the last assembly
+    double nnz_wide;                          // of which in slices that keep full entries
 };
 
 // ---------------------------------------------------------------------------
@@ -89,7 +91,7 @@ struct Seg {
     int ncell;
     int n, npad;       // atoms, padded to TILE
     int tile0, ntile;  // this segment's range in the tile table
-    int Wl, Ws;        // list capacities (row strides)
+    int Wl, Ws, Wb;    // row strides: Coulomb list, covalent list, bonds
     double Q;          // total charge
     double skin;
     // caller arrays (set per call)
@@ -121,20 +123,29 @@ struct Seg {
     int *hcnt;         // [npad]
     uint32_t *hidx;    // [npad * Wl]
     void *Hr;          // [npad * Wl] float / double
+    // In the sliced copy the neighbour row is stored as a 16-bit offset from
+    // the slice's first row (hs16, offset + 32768) when every entry of the
+    // slice lies within that window (swide = 0), else as the full entry
+    // (hsidx); hwide flags the rows that need the full form.
     uint32_t *hsidx;   // [npad * Wl]
+    uint16_t *hs16;    // [npad * Wl]
+    uint8_t *hwide;    // [npad]
+    uint8_t *swide;    // [npad / SLICE]
     void *H;           // [npad * Wl] float / double
     // covalent list: r < S_ij + skin at the last build, row-major, stride Ws
     int *scnt;         // [npad]
     uint32_t *sidx;    // [npad * Ws]
     uint8_t *srev;     // [npad * Ws]: slot of the reverse entry in the partner's row
     // Bonds of the current step: the covalent-list entries inside S_ij (FP64
-    // distance), compacted in list order; cmap maps each list slot to its
-    // bond index (255: outside), bsrev is the list slot of the reverse entry,
-    // brev the bond index of the reverse bond in the partner's row.
+    // distance), compacted in list order into rows of stride Wb; cmap maps
+    // each list slot to its bond index (255: outside) and bsrev holds each
+    // bond's reverse list slot, so the reverse bond of (m, e) in the partner
+    // i's row is cmap[i][bsrev[m][e]].
     int *bcnt;         // [npad]
-    uint32_t *bidx;    // [npad * Ws]
-    uint8_t *cmap, *bsrev, *brev;   // [npad * Ws]
-    void *slot;        // [npad * Ws] per bond, float4 / double4: b, P1, P2, -
+    uint32_t *bidx;    // [npad * Wb]
+    uint8_t *bsrev;    // [npad * Wb]
+    uint8_t *cmap;     // [npad * Ws]
+    void *slot;        // [npad * Wb] per bond, float4 / double4: b, P1, P2, -
     double *ecov;      // [npad]
     double *Fcov;      // SoA [3 npad]
     double *q, *r, *p, *s, *jd;          // [npad]

@@ -28,7 +28,7 @@ struct AdjWs {
     double *v;        // dL/dF in the sorted frame, SoA [3 npad]
     double *a;        // adjoint charge source [npad]
     double *lam;      // adjoint charges [npad]
-    double *slotd;    // dual slot coefficients (b, P1, P2 as value/derivative) [npad * Ws * 6]
+    double *slotd;    // dual bond coefficients (b, P1, P2 as value/derivative) [npad * Wb * 6]
     double *scal;     // [0] q* re-projection, [1] lambda re-projection
     double *grad;     // dL/dtheta accumulators [64]
     double w;         // dL/dE
@@ -140,8 +140,8 @@ __global__ void __launch_bounds__(TILE) k_bond_dual(const Tile *tiles, Seg *segs
     double ew = 0.0;
     if (s < S.n) {
         const double4 *xs = S.xs64;
-        const uint32_t *row = S.bidx + (size_t)s * S.Ws;
-        double *slot = A.slotd + (size_t)s * S.Ws * 6;
+        const uint32_t *row = S.bidx + (size_t)s * S.Wb;
+        double *slot = A.slotd + (size_t)s * S.Wb * 6;
         const double4 li = xs[s];
         const int ti = (int)li.w;
         const int ns = S.bcnt[s];
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov_dual(const Tile *tiles, Seg 
         const double4 lm = xs[m];
         const int tm = (int)lm.w;
         const int ns = S.bcnt[m];
-        const uint32_t *row = S.bidx + (size_t)m * S.Ws;
+        const uint32_t *row = S.bidx + (size_t)m * S.Wb;
         Dual fx(0.0), fy(0.0), fz(0.0);
         for (int e = 0; e < ns; e++) {
             const uint32_t ent = row[e];
@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov_dual(const Tile *tiles, Seg 
             const double r2 = d.x * d.x + d.y * d.y + d.z * d.z;
             if (r2 >= P.Sc[pp].v * P.Sc[pp].v) continue;
             const double r = ::sqrt(r2), ir = 1.0 / r;
-            const double *sv = A.slotd + ((size_t)m * S.Ws + e) * 6;
+            const double *sv = A.slotd + ((size_t)m * S.Wb + e) * 6;
             const Dual b = slotd_get(sv), P1 = slotd_get(sv + 2), P2 = slotd_get(sv + 4);
             const Dual dv = pair_dvdr<Dual>(P, pp, Dual(r), b) * ir;
             Dual ax = dv * d.x, ay = dv * d.y, az = dv * d.z;
@@ -257,14 +257,14 @@ __global__ void __launch_bounds__(TILE) k_force_cov_dual(const Tile *tiles, Seg 
             if (r2 >= P.Sc[pp].v * P.Sc[pp].v) continue;
             const double r = ::sqrt(r2), ir = 1.0 / r;
             const R3<double> d = {-dmi.x, -dmi.y, -dmi.z};
-            const int srev = S.brev[(size_t)m * S.Ws + e];
+            const int srev = reverse_bond(S, m, e, i);
             if (srev >= S.bcnt[i]) continue;                 // (a reverse always exists)
-            const double *sv = A.slotd + ((size_t)i * S.Ws + srev) * 6;
+            const double *sv = A.slotd + ((size_t)i * S.Wb + srev) * 6;
             const Dual b = slotd_get(sv), P1 = slotd_get(sv + 2), P2 = slotd_get(sv + 4);
             const Dual dv = pair_dvdr<Dual>(P, pp, Dual(r), b) * ir;
             Dual ax = -dv * d.x, ay = -dv * d.y, az = -dv * d.z;
             const int ni = S.bcnt[i];
-            const uint32_t *rowi = S.bidx + (size_t)i * S.Ws;
+            const uint32_t *rowi = S.bidx + (size_t)i * S.Wb;
             const R3<Dual> dd = {Dual(d.x), Dual(d.y), Dual(d.z)};
             for (int t = 0; t < ni; t++) {
                 if (t == srev) continue;
@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov_dual(const Tile *tiles, Seg 
                 ax -= P1 * gj[0].x + P2 * gj[1].x;
                 ay -= P1 * gj[0].y + P2 * gj[1].y;
                 az -= P1 * gj[0].z + P2 * gj[1].z;
-                const double *sk = A.slotd + ((size_t)i * S.Ws + t) * 6;
+                const double *sk = A.slotd + ((size_t)i * S.Wb + t) * 6;
                 const Dual K1 = slotd_get(sk + 2), K2 = slotd_get(sk + 4);
                 trip_grad<Dual>(P, ti, pp, ddk, Dual(rk), dd, Dual(r), gj, gk);
                 ax -= K1 * gk[0].x + K2 * gk[1].x;

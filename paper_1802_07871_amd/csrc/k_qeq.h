@@ -92,7 +92,10 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
     for (int k = threadIdx.x / LPR; k < TILE; k += G) {
         const int s = T.row0 + k;
         if (s >= S.n) {
-            if (s < S.npad && lane == 0) S.hcnt[s] = 0;
+            if (s < S.npad && lane == 0) {
+                S.hcnt[s] = 0;
+                S.hwide[s] = 0;
+            }
             continue;                          // the whole group skips together
         }
         const V4 li = xs[s];
@@ -103,6 +106,8 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
         R *vrow = Hr + (size_t)s * S.Wl;
         double acc = 0.0;
         int pos = 0;
+        bool wide = false;
+        const int sbase = s & ~(SLICE - 1);
         for (int e0 = 0; e0 < cnt; e0 += LPR) {
             const int e = e0 + lane;
             bool in = false;
@@ -125,13 +130,17 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
                 hrow[at] = ent;
                 vrow[at] = c;
                 acc += (double)c * S.q[j];
+                const int off = j - sbase;
+                wide = wide || off < -32768 || off > 32767;
             }
             pos += __popc(gm);
         }
         acc = group_sum<LPR>(acc);
+        wide = group_ballot<LPR>(wide) != 0u;
         if (lane == 0) {
             const double qs = S.q[s];
             S.hcnt[s] = pos;
+            S.hwide[s] = wide ? 1 : 0;
             S.jd[s] = PD.J[ti];
             S.r[s] = -(PD.J[ti] * qs + acc + PD.chi[ti]) + mprev;
             S.p[s] = 0.0;
@@ -167,6 +176,10 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
     const bool live = own < S.n;
     const int own_cnt = live ? S.hcnt[own] : 0;
     cnt_lds[threadIdx.x] = own_cnt;
+    // a wave is a slice: the 16-bit form unless one of its rows needs the full one
+    const bool swide = __ballot(live && S.hwide[own] != 0) != 0ull;
+    if ((threadIdx.x & (SLICE - 1)) == 0) S.swide[own / SLICE] = swide ? 1 : 0;
+    const int sbase = own & ~(SLICE - 1);
     int m = own_cnt;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
@@ -195,7 +208,8 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
         for (int e = 0; e < lim; e++) {
             const uint32_t ent = ci[threadIdx.x][e];
             const R v = cv[threadIdx.x][e];
-            S.hsidx[b0 + (size_t)(E0 + e) * SLICE] = ent;
+            if (swide) S.hsidx[b0 + (size_t)(E0 + e) * SLICE] = ent;
+            else S.hs16[b0 + (size_t)(E0 + e) * SLICE] = (uint16_t)((int)(ent & J_MASK) - sbase + 32768);
             H[b0 + (size_t)(E0 + e) * SLICE] = v;
             const unsigned col = (unsigned)((int)(ent & J_MASK) - bbase);
             if (col < (unsigned)BK) {
@@ -243,6 +257,7 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
         S.m1[own] = m1;
         v[0] = S.r[own] * m1;
         v[1] = (double)own_cnt;
+        v[2] = swide ? (double)own_cnt : 0.0;
         v[4] = m1;
     } else if (own < S.npad) {
         S.m1[own] = 0.0;
@@ -274,6 +289,7 @@ __global__ void k_fin_w0(const int *seg_ids, Seg *segs)
         st->sdinv = tot[4];
         st->w = tot[0] / tot[4];
         st->nnz_coul = tot[1];
+        st->nnz_wide = tot[2];
     }
 }
 
@@ -345,6 +361,36 @@ __global__ void __launch_bounds__(TILE) k_cg_dir(const Tile *tiles, Seg *segs)
 // s = H p and the tile's share of p^T s, one row per lane; U entries of the
 // row are loaded before their products are summed, so U gathers of p are in
 // flight per lane (U accumulators, combined in a fixed order at the end).
+template <typename R, int U, typename IDX>
+__device__ __forceinline__ double spmv_row(const double *p, const IDX *row, const R *hrow, int cnt, int jbase)
+{
+    double acc[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) acc[u] = 0.0;
+    int e = 0;
+    for (; e + U <= cnt; e += U) {
+        IDX jj[U];
+        R hh[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            jj[u] = row[(size_t)(e + u) * SLICE];
+            hh[u] = hrow[(size_t)(e + u) * SLICE];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) acc[u] += (double)hh[u] * p[jbase + (int)(jj[u] & J_MASK)];
+    }
+    for (; e < cnt; e++) acc[0] += (double)hrow[(size_t)e * SLICE] * p[jbase + (int)(row[(size_t)e * SLICE] & J_MASK)];
+    double a = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; u++) a += acc[u];
+    return a;
+}
+
+// s = H p and the tile's share of p^T s, one row per lane over the sliced
+// copy; U entries of the row are loaded before their products are summed, so
+// U gathers of p are in flight per lane (U accumulators, combined in a fixed
+// order at the end).  A slice reads 16-bit row offsets (6 bytes per entry)
+// unless it needs the full entries.
 template <typename R, int U>
 __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
 {
@@ -355,31 +401,13 @@ __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
     const int s = T.row0 + threadIdx.x;
     double pap = 0.0;
     if (s < S.n) {
-        const double *p = S.p;
         const size_t b0 = slice_base(s, S.Wl);
-        const uint32_t *row = S.hsidx + b0;
         const R *hrow = reinterpret_cast<const R *>(S.H) + b0;
         const int cnt = S.hcnt[s];
-        double acc[U];
-#pragma unroll
-        for (int u = 0; u < U; u++) acc[u] = 0.0;
-        int e = 0;
-        for (; e + U <= cnt; e += U) {
-            uint32_t jj[U];
-            R hh[U];
-#pragma unroll
-            for (int u = 0; u < U; u++) {
-                jj[u] = row[(size_t)(e + u) * SLICE];
-                hh[u] = hrow[(size_t)(e + u) * SLICE];
-            }
-#pragma unroll
-            for (int u = 0; u < U; u++) acc[u] += (double)hh[u] * p[jj[u] & J_MASK];
-        }
-        for (; e < cnt; e++) acc[0] += (double)hrow[(size_t)e * SLICE] * p[row[(size_t)e * SLICE] & J_MASK];
-        double a = 0.0;
-#pragma unroll
-        for (int u = 0; u < U; u++) a += acc[u];
-        const double ps = p[s];
+        const double a = S.swide[s / SLICE]
+                             ? spmv_row<R, U, uint32_t>(S.p, S.hsidx + b0, hrow, cnt, 0)
+                             : spmv_row<R, U, uint16_t>(S.p, S.hs16 + b0, hrow, cnt, (s & ~(SLICE - 1)) - 32768);
+        const double ps = S.p[s];
         const double y = S.jd[s] * ps + a;
         S.s[s] = y;
         pap = ps * y;

@@ -142,50 +142,15 @@ __device__ __forceinline__ void load_dtab2(const Seg &S, typename Vec4<R>::type 
     __syncthreads();
 }
 
-// Bonds of the step: the covalent-list entries inside S_ij, by the FP64
-// distance that the bond pass uses, compacted in list order.  Every loop
-// over bonds and triplets then runs over bonds only (the skin shell of the
-// covalent list, e.g. the twelve second neighbours of Si in SiC, drops out).
-__global__ void __launch_bounds__(TILE) k_bcompact(const Tile *tiles, Seg *segs, Params<double> P)
-{
-    const Tile T = my_tile(tiles);
-    const Seg &S = segs[T.seg];
-    __shared__ double4 dtab[NCODE];
-    load_dtab2<double>(S, dtab);
-    const int s = T.row0 + threadIdx.x;
-    if (s >= S.n) {
-        if (s < S.npad) S.bcnt[s] = 0;
-        return;
-    }
-    const double4 *xs = S.xs64;
-    const size_t rb = (size_t)s * S.Ws;
-    const double4 li = xs[s];
-    const int ti = (int)li.w;
-    const int ns = S.scnt[s];
-    int c = 0;
-    for (int e = 0; e < ns; e++) {
-        const uint32_t ent = S.sidx[rb + e];
-        const double4 lj = xs[ent & J_MASK];
-        const int pp = ti * 2 + (int)lj.w;
-        const R3<double> d = pair_vec<double>(li, lj, dtab[ent >> CODE_SHIFT]);
-        const double r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-        if (r2 < P.Sc[pp] * P.Sc[pp]) {
-            S.bidx[rb + c] = ent;
-            S.bsrev[rb + c] = S.srev[rb + e];
-            S.cmap[rb + e] = (uint8_t)c;
-            c++;
-        } else {
-            S.cmap[rb + e] = 255;
-        }
-    }
-    S.bcnt[s] = c;
-}
-
+// Bond pass.  First the bonds of the step: the covalent-list entries inside
+// S_ij, by the FP64 distance used below, compacted in list order (so every
+// loop over bonds and triplets runs over bonds only; the skin shell of the
+// covalent list, e.g. the twelve second neighbours of Si in SiC, drops out),
+// with the slot map that lets the force gather find each bond's reverse.
 // The bond pass runs in FP64 from the FP64 local coordinates: it is a small
 // share of the step (a few bonds per atom), and FP64 keeps the energy free of
 // FP32 rounding in zeta, b and the large, cancelling fR and b fA terms.  The
-// coefficients are stored in the pair precision R for the force gather.  It
-// also resolves, per bond, the bond index of its reverse in the partner's row.
+// coefficients are stored in the pair precision R for the force gather.
 template <typename R>
 __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Params<double> P)
 {
@@ -196,21 +161,46 @@ __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Par
     load_dtab2<double>(S, dtab);
     const int s = T.row0 + threadIdx.x;
     if (s >= S.n) {
-        if (s < S.npad) S.ecov[s] = 0.0;
+        if (s < S.npad) {
+            S.ecov[s] = 0.0;
+            S.bcnt[s] = 0;
+        }
         return;
     }
     const double4 *xs = S.xs64;
-    const size_t rb = (size_t)s * S.Ws;
-    V4 *slot = reinterpret_cast<V4 *>(S.slot) + rb;
-    const uint32_t *row = S.bidx + rb;
     const double4 li = xs[s];
     const int ti = (int)li.w;
-    const int nb = S.bcnt[s];
+    const size_t rl = (size_t)s * S.Ws, rb = (size_t)s * S.Wb;
+    const int ns = S.scnt[s];
+    int nb = 0;
+    for (int e = 0; e < ns; e++) {
+        const uint32_t ent = S.sidx[rl + e];
+        const double4 lj = xs[ent & J_MASK];
+        const int pp = ti * 2 + (int)lj.w;
+        const R3<double> d = pair_vec<double>(li, lj, dtab[ent >> CODE_SHIFT]);
+        const double r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+        uint8_t c = 255;
+        if (r2 < P.Sc[pp] * P.Sc[pp]) {
+            if (nb < S.Wb) {
+                S.bidx[rb + nb] = ent;
+                S.bsrev[rb + nb] = S.srev[rl + e];
+                c = (uint8_t)nb;
+            }
+            nb++;
+        }
+        S.cmap[rl + e] = c;
+    }
+    if (nb > S.Wb) {
+        atomicOr(&S.sst->status, ST_OVERFLOW);
+        nb = S.Wb;
+    }
+    S.bcnt[s] = nb;
+    V4 *slot = reinterpret_cast<V4 *>(S.slot) + rb;
+    const uint32_t *row = S.bidx + rb;
     double ecov = 0.0;
     for (int e = 0; e < nb; e++) {
         const uint32_t ent = row[e];
-        const int j = (int)(ent & J_MASK);
-        const double4 lj = xs[j];
+        const double4 lj = xs[ent & J_MASK];
         const int pp = ti * 2 + (int)lj.w;
         const R3<double> d = pair_vec<double>(li, lj, dtab[ent >> CODE_SHIFT]);
         const double r = sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
@@ -244,9 +234,14 @@ __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Par
         out.z = (R)(-0.5 * fc * fA * db2);
         out.w = (R)0;
         slot[e] = out;
-        S.brev[rb + e] = S.cmap[(size_t)j * S.Ws + S.bsrev[rb + e]];
     }
     S.ecov[s] = ecov;
+}
+
+// Bond index, in the partner i's row, of the reverse of bond (m, e)
+__device__ __forceinline__ int reverse_bond(const Seg &S, int m, int e, int i)
+{
+    return S.cmap[(size_t)i * S.Ws + S.bsrev[(size_t)m * S.Wb + e]];
 }
 
 // pair-term derivative dV/dr of 1/2 fc (fR - b fA) at fixed b
@@ -276,7 +271,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
     const V4 lm = xs[m];
     const int tm = (int)lm.w;
     const int nb = S.bcnt[m];
-    const size_t rb = (size_t)m * S.Ws;
+    const size_t rb = (size_t)m * S.Wb;
     const uint32_t *row = S.bidx + rb;
     double fx = 0, fy = 0, fz = 0;
     // m as the centre of its own bonds
@@ -314,12 +309,12 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
         const V4 li = xs[i];
         const int ti = (int)li.w, pp = ti * 2 + tm;
         const int ni = S.bcnt[i];
-        const int rv = S.brev[rb + e];                        // bond (i -> m) in row i
+        const int rv = reverse_bond(S, m, e, i);              // bond (i -> m) in row i
         if (rv >= ni) continue;                               // (a reverse always exists)
         const R3<R> dmi = pair_vec<R>(lm, li, dtab[ent >> CODE_SHIFT]);
         const R r = dev_sqrt(dmi.x * dmi.x + dmi.y * dmi.y + dmi.z * dmi.z), ir = (R)1 / r;
         const R3<R> d = {-dmi.x, -dmi.y, -dmi.z};            // i -> m
-        const size_t ri = (size_t)i * S.Ws;
+        const size_t ri = (size_t)i * S.Wb;
         const V4 sv = slot[ri + rv];
         const R dv = pair_dvdr(P, pp, r, sv.x) * ir;
         R ax = -dv * d.x, ay = -dv * d.y, az = -dv * d.z;

@@ -295,7 +295,6 @@ int server_tick(ctbop_server *S, const Params<R> &prm)
         hipLaunchKernelGGL((k_build<R, BUILD_L>), g, b, 0, st, T, S->dsegs, prm);
         hipLaunchKernelGGL(k_rev, g, b, 0, st, T, S->dsegs);
         hipLaunchKernelGGL(k_mark_built, dim3((nis + 63) / 64), dim3(64), 0, st, sid, S->dsegs, nis);
-        hipLaunchKernelGGL(k_bcompact, g, b, 0, st, T, S->dsegs, ctx->pd);
         hipLaunchKernelGGL((k_bond<R>), g, b, 0, st, T, S->dsegs, ctx->pd);
         hipLaunchKernelGGL((k_assemble<R, LPR>), g, b, 0, st, T, S->dsegs, ctx->pd);
         hipLaunchKernelGGL((k_hslice<R>), g, b, 0, st, T, S->dsegs);
