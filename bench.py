@@ -304,6 +304,27 @@ def fit_bench(ct, theta, count: int = 256, fd_configs: int = 16):
                                                              "max_rel_err": max(c["rel_err"] for c in check.values())}}
 
 
+def measure_copy_peak(torch, mib: int = 2048, reps: int = 10):
+    """Device-to-device copy bandwidth on this GPU (read + write bytes per
+    second, best of `reps` copies of `mib` MiB), the practical HBM ceiling
+    the roofline fractions can be read against."""
+    n = (mib << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = 0.0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = max(best, 2.0 * n * 8 / (e0.elapsed_time(e1) / 1e3) / 1e9)
+    del src, dst
+    torch.cuda.empty_cache()
+    return best
+
+
 def cpu_baseline(theta, nx: int, nsteps: int):
     """The CPU oracle (FP64, OpenMP) on a bounded sample of the same workload:
     the same stepped, depleted slab at nx x nx cells, nsteps MD steps."""
@@ -384,6 +405,7 @@ def main():
         torch.cuda.synchronize()
         print(f"bench: calibration copy of {nb} bytes done", file=sys.stderr, flush=True)
         del src, dst
+    copy_peak = measure_copy_peak(torch)
     theta = PR.load()
     s = workload(args)
     n = s.n
@@ -465,6 +487,7 @@ def main():
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(),
+                     "measured_copy_peak_GBps": copy_peak,
                      "kernel": "k_spmv (charge-solve H p)", "bytes_per_launch": spmv_bytes, "launches": iters,
                      "avg_launch_us": avg_s * 1e6},
         "roofline_force": {"bound": "hbm", "achieved": force_bytes / f_avg / 1e9 if fcnt else None,

@@ -16,7 +16,7 @@ def hipcc_cmd(out: str) -> list[str]:
     return ["hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
             # packed FP32 instructions stay off in every kernel
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+            "-Wall", "-Werror=uninitialized", "-Wno-unused-function", "-Wno-unused-variable",
             os.path.join(CSRC, "ctbop.hip"), "-o", out]
 
 

@@ -59,8 +59,26 @@ void fill_params_dual(const double *theta, int k, const ctbop_opts &o, Params<Du
     P.close2 = 0.25f;
 }
 
+// parameter classes of the flat layout
+bool is_covalent(int k)
+{
+    if (k == 52 || k == 55) return true;
+    if (k >= 52) return false;
+    return (k % 26) <= 20;
+}
+bool is_coulomb(int k) { return k == 53 || k == 54 || (k < 52 && k % 26 == 23); }
+constexpr int N_COVALENT = 44, N_COULOMB = 4;
+
+// The dual passes take a chunk of parameters per launch; the chunk is as
+// large as fits this budget of dual bond coefficients (all 44 covalent
+// parameters for a few thousand atoms, one at a time at a million).
+constexpr size_t DUAL_SLOT_BUDGET = size_t(512) << 20;
+
 struct AdjLayout {
-    size_t off_v, off_a, off_lam, off_slot, off_scal, off_grad, off_seg, off_sst, bytes;
+    size_t off_v, off_a, off_lam, off_slot, off_scal, off_grad, off_seg, off_sst, off_pk, off_kidx, off_ppart, bytes;
+    size_t slot_stride;   // doubles per chunk member
+    int chunk;            // covalent parameters per launch
+    int cap;              // parameter sets held (>= chunk, >= N_COULOMB)
 };
 
 AdjLayout adj_layout(const Layout &L)
@@ -73,10 +91,16 @@ AdjLayout adj_layout(const Layout &L)
         o = align_up(o + b, 256);
         return at;
     };
+    A.slot_stride = 6 * np * (size_t)L.seg.Wb;
+    A.chunk = (int)std::max<size_t>(1, std::min<size_t>(N_COVALENT, DUAL_SLOT_BUDGET / (8 * A.slot_stride)));
+    A.cap = std::max(A.chunk, N_COULOMB);
     A.off_v = take(8 * 3 * np);
     A.off_a = take(8 * np);
     A.off_lam = take(8 * np);
-    A.off_slot = take(8 * 6 * np * (size_t)L.seg.Wb);
+    A.off_slot = take(8 * A.slot_stride * (size_t)A.chunk);
+    A.off_pk = take(sizeof(Params<Dual>) * (size_t)A.cap);
+    A.off_kidx = take(sizeof(int) * (size_t)A.cap);
+    A.off_ppart = take(8 * (size_t)L.seg.ntile * (size_t)A.cap);
     A.off_scal = take(8 * 8);
     A.off_grad = take(8 * 64);
     A.off_seg = take(sizeof(Seg));
@@ -84,15 +108,6 @@ AdjLayout adj_layout(const Layout &L)
     A.bytes = o;
     return A;
 }
-
-// parameter classes of the flat layout
-bool is_covalent(int k)
-{
-    if (k == 52 || k == 55) return true;
-    if (k >= 52) return false;
-    return (k % 26) <= 20;
-}
-bool is_coulomb(int k) { return k == 53 || k == 54 || (k < 52 && k % 26 == 23); }
 
 template <typename R>
 int launch_param_grad(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, char *adj, size_t adj_bytes, double dLdE,
@@ -105,6 +120,11 @@ int launch_param_grad(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, char *adj, 
     A.a = (double *)(adj + AL.off_a);
     A.lam = (double *)(adj + AL.off_lam);
     A.slotd = (double *)(adj + AL.off_slot);
+    A.slot_stride = AL.slot_stride;
+    A.pk = (const Params<Dual> *)(adj + AL.off_pk);
+    A.kidx = (const int *)(adj + AL.off_kidx);
+    A.ppart = (double *)(adj + AL.off_ppart);
+    A.ptile = P.L.ntile;
     A.scal = (double *)(adj + AL.off_scal);
     A.grad = (double *)(adj + AL.off_grad);
     A.w = dLdE;
@@ -157,20 +177,41 @@ int launch_param_grad(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, char *adj, 
     // closed-form chi, J, E0 terms
     hipLaunchKernelGGL(k_self_terms, g, b, 0, st, P.dtiles, P.dseg, A);
     hipLaunchKernelGGL(k_fin_grad<6>, g1, b, 0, st, sid, P.dseg, A, 21, 22, 24, 26 + 21, 26 + 22, 26 + 24);
-    // forward-mode passes over the explicit dependence
-    Params<Dual> pdual;
+    // forward-mode passes over the explicit dependence, a chunk of parameters
+    // per launch (blockIdx.y = member); every set is filled on the host first
+    std::vector<int> cov, coul;
     for (int k = 0; k < CTBOP_N_PARAMS; k++) {
-        if (is_covalent(k)) {
-            fill_params_dual(ctx->theta, k, ctx->opts, pdual);
-            hipLaunchKernelGGL(k_bond_dual, g, b, 0, st, P.dtiles, P.dseg, pdual, A);
-            hipLaunchKernelGGL(k_fin_grad<1>, g1, b, 0, st, sid, P.dseg, A, k, -1, -1, -1, -1, -1);
-            hipLaunchKernelGGL(k_force_cov_dual, g, b, 0, st, P.dtiles, P.dseg, pdual, A);
-            hipLaunchKernelGGL(k_fin_grad<1>, g1, b, 0, st, sid, P.dseg, A, k, -1, -1, -1, -1, -1);
-        } else if (is_coulomb(k)) {
-            fill_params_dual(ctx->theta, k, ctx->opts, pdual);
-            hipLaunchKernelGGL((k_coul_dual<R, LPR>), g, b, 0, st, P.dtiles, P.dseg, pdual, A);
-            hipLaunchKernelGGL(k_fin_grad<1>, g1, b, 0, st, sid, P.dseg, A, k, -1, -1, -1, -1, -1);
-        }
+        if (is_covalent(k)) cov.push_back(k);
+        else if (is_coulomb(k)) coul.push_back(k);
+    }
+    std::vector<Params<Dual>> hpk(cov.size() + coul.size());
+    std::vector<int> hk(cov.size() + coul.size());
+    for (size_t m = 0; m < cov.size(); m++) {
+        fill_params_dual(ctx->theta, cov[m], ctx->opts, hpk[m]);
+        hk[m] = cov[m];
+    }
+    for (size_t m = 0; m < coul.size(); m++) {
+        fill_params_dual(ctx->theta, coul[m], ctx->opts, hpk[cov.size() + m]);
+        hk[cov.size() + m] = coul[m];
+    }
+    Params<Dual> *dpk = (Params<Dual> *)(adj + AL.off_pk);
+    int *dk = (int *)(adj + AL.off_kidx);
+    for (size_t c0 = 0; c0 < cov.size(); c0 += AL.chunk) {
+        const int m = (int)std::min<size_t>(AL.chunk, cov.size() - c0);
+        HIPCHK(hipMemcpyAsync(dpk, &hpk[c0], sizeof(Params<Dual>) * m, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(dk, &hk[c0], sizeof(int) * m, hipMemcpyHostToDevice, st));
+        const dim3 gm(P.L.ntile, m);
+        hipLaunchKernelGGL(k_bond_dual, gm, b, 0, st, P.dtiles, P.dseg, A);
+        hipLaunchKernelGGL(k_fin_grad_members, dim3(m), b, 0, st, A, P.L.ntile);
+        hipLaunchKernelGGL(k_force_cov_dual, gm, b, 0, st, P.dtiles, P.dseg, A);
+        hipLaunchKernelGGL(k_fin_grad_members, dim3(m), b, 0, st, A, P.L.ntile);
+    }
+    {
+        const int m = (int)coul.size();
+        HIPCHK(hipMemcpyAsync(dpk, &hpk[cov.size()], sizeof(Params<Dual>) * m, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(dk, &hk[cov.size()], sizeof(int) * m, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL((k_coul_dual<R, LPR>), dim3(P.L.ntile, m), b, 0, st, P.dtiles, P.dseg, A);
+        hipLaunchKernelGGL(k_fin_grad_members, dim3(m), b, 0, st, A, P.L.ntile);
     }
     HIPCHK(hipGetLastError());
     int status = 0;

@@ -150,9 +150,11 @@ struct Seg {
     double *Fcov;      // SoA [3 npad]
     double *q, *r, *p, *s, *jd;          // [npad]
     // block-Jacobi preconditioner: the inverse of each diagonal BK x BK block
-    // of H (blocks of BK consecutive sorted rows, symmetric; entry (t, u) of
-    // block b at b*BK*BK + t*BK + u), its row sums m1 = B^-1 1, and y = B^-1 r
-    double *binv;      // [npad * BK]
+    // of H (blocks of BK consecutive sorted rows; entry (t, u) of block b at
+    // b*BK*BK + t*BK + u), computed in FP64, symmetrised and stored in FP32
+    // (so the operator is exactly symmetric); its row sums m1 = M 1 (of the
+    // stored entries, FP64) and y = M r
+    float *binv;       // [npad * BK]
     double *m1, *y;    // [npad]
     double *q_state;   // user order charges of the last solve, for the warm start [n]
     double *q_h1, *q_h2, *q_h3;   // the three solves before it (predictor history) [n]

@@ -28,11 +28,37 @@ struct AdjWs {
     double *v;        // dL/dF in the sorted frame, SoA [3 npad]
     double *a;        // adjoint charge source [npad]
     double *lam;      // adjoint charges [npad]
-    double *slotd;    // dual bond coefficients (b, P1, P2 as value/derivative) [npad * Wb * 6]
     double *scal;     // [0] q* re-projection, [1] lambda re-projection
     double *grad;     // dL/dtheta accumulators [64]
     double w;         // dL/dE
+    // dual passes, a chunk of parameters per launch (blockIdx.y = member)
+    const Params<Dual> *pk;   // the chunk's parameter sets, each seeded in its own parameter
+    const int *kidx;          // the chunk's flat parameter indices
+    double *slotd;            // dual bond coefficients (b, P1, P2 as value/derivative),
+                              // [member][npad * Wb * 6]
+    size_t slot_stride;       // doubles per member
+    double *ppart;            // per-member tile partial sums [member][ptile]
+    int ptile;
 };
+
+// The chunk member's parameter set, staged in LDS (buf) by the whole block
+__device__ __forceinline__ const Params<Dual> &load_member_params(const AdjWs &A, unsigned char *buf)
+{
+    static_assert(sizeof(Params<Dual>) % 4 == 0, "copied as 32-bit words");
+    const int *src = reinterpret_cast<const int *>(A.pk + blockIdx.y);
+    int *dst = reinterpret_cast<int *>(buf);
+    for (int i = threadIdx.x; i < (int)(sizeof(Params<Dual>) / 4); i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+    return *reinterpret_cast<const Params<Dual> *>(buf);
+}
+
+// Block sum of one value per thread into the member's partial for this tile
+__device__ __forceinline__ void member_partial(const AdjWs &A, int tile_local, double v, double *lds)
+{
+    double in[1] = {v}, out[1];
+    block_sum<1>(in, lds, out);
+    if (threadIdx.x == 0) A.ppart[(size_t)blockIdx.y * A.ptile + tile_local] = out[0];
+}
 
 // seeds into the sorted frame; keep the forward charges' re-projection
 __global__ void __launch_bounds__(TILE) k_adj_seed(const Tile *tiles, Seg *segs, AdjWs A, const double *dLdF,
@@ -124,24 +150,26 @@ __global__ void k_adj_keep_lam_shift(const int *seg_ids, Seg *segs, AdjWs A)
 }
 
 // ---------------------------------------------------------------------------
-// dual passes (one parameter each)
+// dual passes (a chunk of parameters per launch, one per blockIdx.y)
 // ---------------------------------------------------------------------------
 
-// Covalent bond pass in dual numbers: per-slot b, P1, P2 and the tile's
-// w dEcov/dtheta.
-__global__ void __launch_bounds__(TILE) k_bond_dual(const Tile *tiles, Seg *segs, Params<Dual> P, AdjWs A)
+// Covalent bond pass in dual numbers: per-bond b, P1, P2 and the tile's
+// w dEcov/dtheta, for the chunk member blockIdx.y.
+__global__ void __launch_bounds__(TILE) k_bond_dual(const Tile *tiles, Seg *segs, AdjWs A)
 {
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     __shared__ double4 dtab[NCODE];
     __shared__ double lds[4];
+    __shared__ __align__(16) unsigned char pbuf[sizeof(Params<Dual>)];
+    const Params<Dual> &P = load_member_params(A, pbuf);
     load_dtab2<double>(S, dtab);
     const int s = T.row0 + threadIdx.x;
     double ew = 0.0;
     if (s < S.n) {
         const double4 *xs = S.xs64;
         const uint32_t *row = S.bidx + (size_t)s * S.Wb;
-        double *slot = A.slotd + (size_t)s * S.Wb * 6;
+        double *slot = A.slotd + blockIdx.y * A.slot_stride + (size_t)s * S.Wb * 6;
         const double4 li = xs[s];
         const int ti = (int)li.w;
         const int ns = S.bcnt[s];
@@ -193,20 +221,22 @@ __global__ void __launch_bounds__(TILE) k_bond_dual(const Tile *tiles, Seg *segs
         }
         ew = A.w * ecov.d;
     }
-    double v1[1] = {ew};
-    tile_partials<1>(S, T.row0 / TILE, v1, lds);
+    member_partial(A, T.row0 / TILE, ew, lds);
 }
 
 __device__ __forceinline__ Dual slotd_get(const double *p) { return Dual(p[0], p[1]); }
 
 // Covalent force gather in dual numbers; the tile's sum of v_m . dF_m/dtheta.
-__global__ void __launch_bounds__(TILE) k_force_cov_dual(const Tile *tiles, Seg *segs, Params<Dual> P, AdjWs A)
+__global__ void __launch_bounds__(TILE) k_force_cov_dual(const Tile *tiles, Seg *segs, AdjWs A)
 {
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     __shared__ double4 dtab[NCODE];
     __shared__ double lds[4];
+    __shared__ __align__(16) unsigned char pbuf[sizeof(Params<Dual>)];
+    const Params<Dual> &P = load_member_params(A, pbuf);
     load_dtab2<double>(S, dtab);
+    const double *slotd = A.slotd + blockIdx.y * A.slot_stride;
     const int m = T.row0 + threadIdx.x;
     double vf = 0.0;
     if (m < S.n) {
@@ -224,7 +254,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov_dual(const Tile *tiles, Seg 
             const double r2 = d.x * d.x + d.y * d.y + d.z * d.z;
             if (r2 >= P.Sc[pp].v * P.Sc[pp].v) continue;
             const double r = ::sqrt(r2), ir = 1.0 / r;
-            const double *sv = A.slotd + ((size_t)m * S.Wb + e) * 6;
+            const double *sv = slotd + ((size_t)m * S.Wb + e) * 6;
             const Dual b = slotd_get(sv), P1 = slotd_get(sv + 2), P2 = slotd_get(sv + 4);
             const Dual dv = pair_dvdr<Dual>(P, pp, Dual(r), b) * ir;
             Dual ax = dv * d.x, ay = dv * d.y, az = dv * d.z;
@@ -259,7 +289,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov_dual(const Tile *tiles, Seg 
             const R3<double> d = {-dmi.x, -dmi.y, -dmi.z};
             const int srev = reverse_bond(S, m, e, i);
             if (srev >= S.bcnt[i]) continue;                 // (a reverse always exists)
-            const double *sv = A.slotd + ((size_t)i * S.Wb + srev) * 6;
+            const double *sv = slotd + ((size_t)i * S.Wb + srev) * 6;
             const Dual b = slotd_get(sv), P1 = slotd_get(sv + 2), P2 = slotd_get(sv + 4);
             const Dual dv = pair_dvdr<Dual>(P, pp, Dual(r), b) * ir;
             Dual ax = -dv * d.x, ay = -dv * d.y, az = -dv * d.z;
@@ -281,7 +311,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov_dual(const Tile *tiles, Seg 
                 ax -= P1 * gj[0].x + P2 * gj[1].x;
                 ay -= P1 * gj[0].y + P2 * gj[1].y;
                 az -= P1 * gj[0].z + P2 * gj[1].z;
-                const double *sk = A.slotd + ((size_t)i * S.Wb + t) * 6;
+                const double *sk = slotd + ((size_t)i * S.Wb + t) * 6;
                 const Dual K1 = slotd_get(sk + 2), K2 = slotd_get(sk + 4);
                 trip_grad<Dual>(P, ti, pp, ddk, Dual(rk), dd, Dual(r), gj, gk);
                 ax -= K1 * gk[0].x + K2 * gk[1].x;
@@ -294,8 +324,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov_dual(const Tile *tiles, Seg 
         }
         vf = A.v[m] * fx.d + A.v[S.npad + m] * fy.d + A.v[2 * S.npad + m] * fz.d;
     }
-    double v1[1] = {vf};
-    tile_partials<1>(S, T.row0 / TILE, v1, lds);
+    member_partial(A, T.row0 / TILE, vf, lds);
 }
 
 // Coulomb kernel in dual numbers (parameters gamma, ke, rc may carry the
@@ -315,13 +344,15 @@ __device__ __forceinline__ Dual coul_dual(const Params<Dual> &P, int pp, double 
 
 // Per row: w/2 q_s q_j dC/dtheta + q_s q_j d(C')/dtheta (v_s . r_hat) - lambda_s q_j dC/dtheta
 template <typename R, int LPR>
-__global__ void __launch_bounds__(TILE) k_coul_dual(const Tile *tiles, Seg *segs, Params<Dual> P, AdjWs A)
+__global__ void __launch_bounds__(TILE) k_coul_dual(const Tile *tiles, Seg *segs, AdjWs A)
 {
     using V4 = typename Vec4<R>::type;
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     __shared__ V4 dtab[NCODE];
     __shared__ double lds[4];
+    __shared__ __align__(16) unsigned char pbuf[sizeof(Params<Dual>)];
+    const Params<Dual> &P = load_member_params(A, pbuf);
     load_dtab2<R>(S, dtab);
     const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
     const double qsh = A.scal[0], lsh = A.scal[1];
@@ -354,8 +385,7 @@ __global__ void __launch_bounds__(TILE) k_coul_dual(const Tile *tiles, Seg *segs
         acc = group_sum<LPR>(acc);
         if (lane == 0) tot += acc;
     }
-    double v1[1] = {tot};
-    tile_partials<1>(S, T.row0 / TILE, v1, lds);
+    member_partial(A, T.row0 / TILE, tot, lds);
 }
 
 // Closed-form self-energy and diagonal terms, per species t:
@@ -391,6 +421,18 @@ __global__ void k_fin_grad(const int *seg_ids, Seg *segs, AdjWs A, int i0, int i
         for (int k = 0; k < K; k++)
             if (idx[k] >= 0) A.grad[idx[k]] += tot[k];
     }
+}
+
+// Add each chunk member's total (its ptile partials, summed in a fixed order)
+// to grad[kidx[member]]; one block per member.
+__global__ void k_fin_grad_members(AdjWs A, int ntile)
+{
+    __shared__ double lds[4];
+    double v[1] = {0.0}, tot[1];
+    const double *pp = A.ppart + (size_t)blockIdx.x * A.ptile;
+    for (int t = threadIdx.x; t < ntile; t += blockDim.x) v[0] += pp[t];
+    block_sum<1>(v, lds, tot);
+    if (threadIdx.x == 0) A.grad[A.kidx[blockIdx.x]] += tot[0];
 }
 
 __global__ void k_zero(double *p, int n)

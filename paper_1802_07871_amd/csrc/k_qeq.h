@@ -245,12 +245,12 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
         __syncthreads();
     }
     double m1 = 0.0;
-    double *bo = S.binv + (size_t)(T.row0 + blk * BK) * BK;
+    float *bo = S.binv + (size_t)(T.row0 + blk * BK) * BK;
 #pragma unroll
     for (int t = 0; t < BK; t++) {
-        const double b = 0.5 * (A[blk][i][t] + A[blk][t][i]);
+        const float b = (float)(0.5 * (A[blk][i][t] + A[blk][t][i]));
         bo[t * BK + i] = b;
-        m1 += b;
+        m1 += (double)b;
     }
     double v[5] = {0, 0, 0, 0, 0};
     if (live) {
@@ -270,10 +270,10 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
 // block must call it; rows past n pass r = 0).
 __device__ __forceinline__ double block_apply(const Seg &S, int s, double r)
 {
-    const double *B = S.binv + (size_t)(s & ~(BK - 1)) * BK + (s & (BK - 1));
+    const float *B = S.binv + (size_t)(s & ~(BK - 1)) * BK + (s & (BK - 1));
     double y = 0.0;
 #pragma unroll
-    for (int t = 0; t < BK; t++) y += B[t * BK] * __shfl(r, t, BK);
+    for (int t = 0; t < BK; t++) y += (double)B[t * BK] * __shfl(r, t, BK);
     return y;
 }
 
