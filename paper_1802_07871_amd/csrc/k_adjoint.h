@@ -110,11 +110,11 @@ __global__ void __launch_bounds__(TILE) k_adj_source(const Tile *tiles, Seg *seg
             R3<R> d;
             const double r = entry_r<R>(li, lj, dtab[ent >> CODE_SHIFT], d);
             if (r >= PD.rc) continue;
-            double dC;
-            coul64(PD, ti * 2 + (int)lj.w, r, dC);
+            double dCr;
+            coul64(PD, ti * 2 + (int)lj.w, r, dCr);
             const double dv = (vx - A.v[j]) * (double)d.x + (vy - A.v[S.npad + j]) * (double)d.y +
                               (vz - A.v[2 * S.npad + j]) * (double)d.z;
-            acc += (S.q[j] + qsh) * dC * dv / r;
+            acc += (S.q[j] + qsh) * dCr * dv;
         }
         acc = group_sum<LPR>(acc);
         if (lane == 0) A.a[s] += acc;

@@ -26,22 +26,31 @@
 namespace ctbop {
 
 // Shielded, tapered Coulomb kernel C(r) = ke T(r/rc) (r^3 + g3)^(-1/3) and
-// dC/dr, evaluated in FP64 for a given distance: the FP32 reciprocal cube
-// root seeds one Newton step, y <- y (4 - u y^3) / 3, which leaves a relative
-// error of ~1e-14, so the only error left in the mixed build is the
+// (dC/dr)/r, evaluated in FP64 for a given distance: an FP32 seed of the
+// reciprocal cube root and one Newton step, y <- y (4 - u y^3) / 3, leave a
+// relative error of ~1e-13, so the only error left in the mixed build is the
 // (unbiased) rounding of r itself.  Summed over ~10^5 charged pairs, a
 // one-sided error of the FP32 functions would otherwise bias the energy.
-__device__ __forceinline__ double coul64(const Params<double> &P, int pp, double r, double &dC)
+// The radial derivative comes divided by r, without a division: with
+// T'(x) = -140 x^3 (1-x)^3 and x = r/rc,
+//   (dC/dr)/r = ke [ -140 x^2 (1-x)^3 y / rc^2 - T r y^4 ].
+__device__ __forceinline__ double rcbrt64(double u)
+{
+    // u^(-1/3) for u = r^3 + g3 > 0 (pairs are never closer than 0.5 A): the
+    // hardware FP32 log2/exp2 seed (~1e-7) and one FP64 Newton step
+    const double y = (double)__builtin_amdgcn_exp2f(-0.333333343f * __builtin_amdgcn_logf((float)u));
+    return y * (4.0 - u * y * y * y) * (1.0 / 3.0);
+}
+
+__device__ __forceinline__ double coul64(const Params<double> &P, int pp, double r, double &dCr)
 {
     const double x = r * P.inv_rc, x2 = x * x, x3 = x2 * x;
     const double om = 1.0 - x, om2 = om * om;
     const double T = om2 * om2 * (1.0 + 4.0 * x + 10.0 * x2 + 20.0 * x3);
-    const double dT = -140.0 * x3 * om2 * om;
     const double u = r * r * r + P.g3[pp];
-    double y = (double)rcbrtf((float)u);
-    y = y * (4.0 - u * y * y * y) * (1.0 / 3.0);
+    const double y = rcbrt64(u);
     const double y2 = y * y;
-    dC = P.ke * (dT * P.inv_rc * y - T * r * r * y2 * y2);
+    dCr = P.ke * (-140.0 * P.inv_rc * P.inv_rc * x2 * om2 * om * y - T * r * y2 * y2);
     return P.ke * T * y;
 }
 
@@ -51,8 +60,7 @@ __device__ __forceinline__ double coul64_val(const Params<double> &P, int pp, do
     const double om = 1.0 - x, om2 = om * om;
     const double T = om2 * om2 * (1.0 + 4.0 * x + 10.0 * x2 + 20.0 * x3);
     const double u = r * r * r + P.g3[pp];
-    double y = (double)rcbrtf((float)u);
-    y = y * (4.0 - u * y * y * y) * (1.0 / 3.0);
+    const double y = rcbrt64(u);
     return P.ke * T * y;
 }
 
@@ -525,12 +533,12 @@ __global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *seg
             R3<R> d;
             const double r = entry_r<R>(li, lj, dtab[ent >> CODE_SHIFT], d);
             if (r >= PD.rc) continue;          // never taken: the rows hold entries inside rc
-            double dC;
-            const double c = coul64(PD, ti * 2 + (int)lj.w, r, dC);
+            double dCr;
+            const double c = coul64(PD, ti * 2 + (int)lj.w, r, dCr);
             const double qj = S.q[j] + qsh;
             ec += c * qj;
             if (j != s) {
-                const double g = qj * dC / r;
+                const double g = qj * dCr;
                 fx += g * (double)d.x;
                 fy += g * (double)d.y;
                 fz += g * (double)d.z;
