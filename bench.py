@@ -304,6 +304,26 @@ def fit_bench(ct, theta, count: int = 256, fd_configs: int = 16):
                                                              "max_rel_err": max(c["rel_err"] for c in check.values())}}
 
 
+def removal_bench(ct, theta, concurrency: int = 32):
+    """The paper's desorption test at the scale of its growth cell: removal
+    energies dE_i = E(X without i) - E(X) of every top-layer Si of a stepped
+    4H-SiC slab (24 x 24 cells x 8 bilayers, 30 % of the top Si removed,
+    ~18k atoms), charges re-equilibrated in every system."""
+    import numpy as np
+    from ctbop_inputs import generators as G
+    s = G.slab_4h(24, 24, 8, step=True, deplete=0.3, seed=1006)
+    cand = np.flatnonzero((s.meta["layer"] == 2 * 8 - 1) & (s.types == 0))
+    pot = ct.Potential(theta)
+    pot.removal_energies(s.pos, s.types, s.box, s.pbc, cand[:4], concurrency=concurrency)   # warm-up
+    t0 = time.perf_counter()
+    E0, dE, it = pot.removal_energies(s.pos, s.types, s.box, s.pbc, cand, concurrency=concurrency)
+    dt = time.perf_counter() - t0
+    return {"atoms": int(s.n), "candidates": int(len(cand)), "seconds": dt, "candidates_per_s": len(cand) / dt,
+            "atoms_per_s": len(cand) * (s.n - 1) / dt, "cg_iters_mean": float(np.mean(it)),
+            "dE_eV": {"min": float(dE.min()), "median": float(np.median(dE)), "max": float(dE.max())},
+            "below_6.5eV": int((dE < 6.5).sum())}
+
+
 def measure_copy_peak(torch, mib: int = 2048, reps: int = 10):
     """Device-to-device copy bandwidth on this GPU (read + write bytes per
     second, best of `reps` copies of `mib` MiB), the practical HBM ceiling
@@ -360,6 +380,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=None)
     ap.add_argument("--no-serving", action="store_true", help="skip the compact serving measurement")
     ap.add_argument("--no-fit", action="store_true", help="skip the fit-batch (parameter gradient) measurement")
+    ap.add_argument("--no-removal", action="store_true", help="skip the removal-energy (desorption) measurement")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (scales HBM byte counters)")
     args = ap.parse_args()
@@ -508,6 +529,10 @@ def main():
         print("bench: fit-batch forward + adjoint", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         out["fit_batch"] = fit_bench(ct, theta)
+    if not args.no_removal:
+        print("bench: removal energies (desorption test)", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        out["removal"] = removal_bench(ct, theta)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(theta, args.cpu_nx, args.cpu_steps)

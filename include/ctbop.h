@@ -253,6 +253,8 @@ typedef struct {
     double        *E_host;        /* outputs (host, may be NULL): must stay valid until */
     double        *F_host;        /* the result is polled; F is 3n SoA, q is n          */
     double        *q_host;
+    const double  *q0_host;       /* NULL, or n starting charges for the charge solve   */
+                                  /* (copied at submit; projected onto total_charge)    */
 } ctbop_request;
 
 typedef struct {
@@ -282,6 +284,31 @@ int ctbop_server_poll(ctbop_server *srv, ctbop_result *out, int max, double wait
 int ctbop_server_stats(ctbop_server *srv, double *out, int nout);
 /* Stop the scheduler (pending requests are dropped) and release host state. */
 int ctbop_server_destroy(ctbop_server *srv);
+
+/* ------------------------------------------------------------------------ */
+/* Removal energies (the paper's Si-desorption test)                          */
+/* ------------------------------------------------------------------------ */
+/* The stability of an atom is the change of the total energy when that atom
+ * is removed (growth-simulation section: Si atoms whose removal costs less
+ * than 6.5 eV are removed, the test repeated every 1 ps).  For every
+ * candidate i this returns dE_i = E(X without atom i) - E(X), both energies
+ * at their own equilibrated charges with the same total charge Q:
+ *   pos_host      3n doubles SoA, types_host n int32 (host, read during the call)
+ *   cand_host     m atom indices (0 <= i < n; repeats allowed)
+ *   E_host        out: E(X);  dE_host: out, m doubles;  iters_host: NULL or m ints,
+ *                 the charge-solve iterations of each leave-one-out system
+ *   arena_dev     caller-owned device memory of at least ctbop_removal_bytes(m) bytes
+ *                 (more lets more leave-one-out systems run at once)
+ * The full system is evaluated once at the head of the arena; the m systems
+ * of n-1 atoms then run as a continuous batch through a server on the rest,
+ * each starting its charge solve from the full system's charges (re-projected
+ * onto Q), which leaves only the local relaxation to solve.  Waits for the
+ * stream; E_INVAL on a bad index, E_NOMEM if the arena is too small. */
+int ctbop_removal_bytes(ctbop_ctx *ctx, int n, const double *box_host, const int *pbc_host, int m, size_t *bytes);
+int ctbop_removal_energies(ctbop_ctx *ctx, int n, const double *pos_host, const int32_t *types_host,
+                           const double *box_host, const int *pbc_host, double total_charge, const int *cand_host,
+                           int m, void *arena_dev, size_t arena_bytes, double *E_host, double *dE_host,
+                           int *iters_host, void *stream);
 
 #ifdef __cplusplus
 }

@@ -213,6 +213,22 @@ def param_derivative(pos, types, box, pbc, params, k, Q=0.0, tol=1e-12, h=1e-30)
     return dict(dE=float(dE[0]), dF=dF, dq=dq, E=float(E[0]), F=F, q=q)
 
 
+def removal_energy(pos, types, box, pbc, params, atoms, Q=0.0, tol=1e-12):
+    """Energy change on eliminating each atom of `atoms`, both systems at their
+    equilibrated charges with total charge Q (growth-simulation section: the
+    stability of a surface Si atom is the total-energy change following its
+    elimination; atoms below a 6.5 eV threshold desorb).  The definition
+    itself: two full evaluations per atom.  Returns (E(X), dE array)."""
+    pos, types, box, pbc = _geom(pos, types, box, pbc)
+    E0 = evaluate(pos, types, box, pbc, params, Q=Q, tol=tol)[0]
+    out = []
+    for i in atoms:
+        keep = np.ones(len(types), dtype=bool)
+        keep[int(i)] = False
+        out.append(evaluate(pos[keep], types[keep], box, pbc, params, Q=Q, tol=tol)[0] - E0)
+    return E0, np.array(out)
+
+
 def dense_kkt_charges(H, chi, Q=0.0):
     """Direct solve of [H 1; 1^T 0][q; -mu] = [-chi; Q] (numpy LU)."""
     n = len(chi)

@@ -54,7 +54,8 @@ class Info(ctypes.Structure):
 _lib = None
 EXPORTS = ("ctbop_default_opts", "ctbop_create", "ctbop_destroy", "ctbop_system_bytes",
            "ctbop_compute_energy_forces_charges", "ctbop_md_run", "ctbop_status", "ctbop_last_error",
-           "ctbop_debug_lists", "ctbop_profile", "ctbop_set_params", "ctbop_param_grad_bytes", "ctbop_param_grad")
+           "ctbop_debug_lists", "ctbop_profile", "ctbop_set_params", "ctbop_param_grad_bytes", "ctbop_param_grad",
+           "ctbop_removal_bytes", "ctbop_removal_energies")
 
 
 def lib():
@@ -80,6 +81,8 @@ def lib():
         L.ctbop_set_params.argtypes = [vp, vp, i32]
         L.ctbop_param_grad_bytes.argtypes = [vp, i32, vp, vp, ctypes.POINTER(sz)]
         L.ctbop_param_grad.argtypes = [vp, i32, vp, vp, vp, sz, vp, sz, dbl, vp, vp, vp, ctypes.POINTER(i32), vp]
+        L.ctbop_removal_bytes.argtypes = [vp, i32, vp, vp, i32, ctypes.POINTER(sz)]
+        L.ctbop_removal_energies.argtypes = [vp, i32, vp, vp, vp, vp, dbl, vp, i32, vp, sz, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -257,6 +260,31 @@ class Potential:
         _check(rc)
         return (x.reshape(3, n).t().contiguous(), v.reshape(3, n).t().contiguous(),
                 F.reshape(3, n).t().contiguous(), q, thermo, info.as_dict())
+
+    def removal_energies(self, pos, types, box, pbc, candidates, Q=0.0, concurrency: int = 16):
+        """dE_i = E(X without atom i) - E(X) for every candidate i, charges
+        re-equilibrated in both (the desorption test).  pos (n,3), types (n,)
+        numpy.  Returns (E(X), dE (m,), charge-solve iterations (m,))."""
+        torch = _torch()
+        pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+        n = len(pos)
+        soa = np.ascontiguousarray(pos.T).reshape(-1)
+        ty = np.ascontiguousarray(np.asarray(types, dtype=np.int32))
+        cand = np.ascontiguousarray(np.asarray(candidates, dtype=np.int32))
+        m = len(cand)
+        b, p = _box_pbc(box, pbc)
+        nb = ctypes.c_size_t()
+        _check(lib().ctbop_removal_bytes(self.ctx, n, b.ctypes.data, p.ctypes.data, max(1, min(m, concurrency)),
+                                         ctypes.byref(nb)))
+        arena = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+        E = np.zeros(1)
+        dE = np.zeros(max(m, 1))
+        it = np.zeros(max(m, 1), dtype=np.int32)
+        _check(lib().ctbop_removal_energies(self.ctx, n, soa.ctypes.data, ty.ctypes.data, b.ctypes.data,
+                                            p.ctypes.data, float(Q), cand.ctypes.data, m,
+                                            ctypes.c_void_p(arena.data_ptr()), int(nb.value), E.ctypes.data,
+                                            dE.ctypes.data, it.ctypes.data, _stream()))
+        return float(E[0]), dE[:m], it[:m]
 
     KERNELS = ("spmv", "force_coul", "assemble", "bond", "force_cov", "cg_update", "cg_dir", "build", "hslice")
 

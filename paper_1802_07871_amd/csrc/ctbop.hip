@@ -800,4 +800,5 @@ int ctbop_debug_lists(ctbop_ctx *ctx, int n, void *sys, size_t sys_bytes, int lo
 } // extern "C"
 
 #include "server.h"
+#include "removal.h"
 #include "adjoint_host.h"

@@ -45,6 +45,7 @@ struct SrvReq {
     int pbc[3];
     double Q;
     long sys_id;
+    std::vector<double> q0;         // starting charges (user order), or empty
     double *E_out, *F_out, *q_out;
     double t_submit, t_admit;
 };
@@ -234,8 +235,12 @@ int admit_one(ctbop_server *S, SrvReq &r, bool &placed)
     if (fresh)
         hipLaunchKernelGGL(k_reset_state, dim3((sl.L.ntile + 255) / 256), dim3(256), 0, S->stream, sd.sst,
                            (Tile *)(base + iob + sl.L.off_tiles), sl.L.ntile, (int *)(base + iob + sl.L.off_segid));
-    // a retained system starts its charge solve from its last charges
-    hipLaunchKernelGGL(k_set_warm, dim3(1), dim3(1), 0, S->stream, sd.sst, fresh ? 0 : 1);
+    // starting charges given with the request replace the warm-start state;
+    // a retained system otherwise starts from its last charges
+    const bool given = !sl.req.q0.empty();
+    if (given)
+        HIPCHK(hipMemcpyAsync(sd.q_state, sl.req.q0.data(), 8 * (size_t)n, hipMemcpyHostToDevice, S->stream));
+    hipLaunchKernelGGL(k_set_warm, dim3(1), dim3(1), 0, S->stream, sd.sst, (fresh && !given) ? 0 : 1);
     HIPCHK(hipGetLastError());
     S->admitted++;
     placed = true;
@@ -505,6 +510,7 @@ int ctbop_server_submit(ctbop_server *S, const ctbop_request *rq, long *ticket)
     for (int a = 0; a < 3; a++) r.pbc[a] = rq->pbc[a];
     r.Q = rq->total_charge;
     r.sys_id = rq->system_id;
+    if (rq->q0_host) r.q0.assign(rq->q0_host, rq->q0_host + rq->n);
     r.E_out = rq->E_host;
     r.F_out = rq->F_host;
     r.q_out = rq->q_host;

@@ -14,7 +14,7 @@ class Request(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("pos_host", ctypes.c_void_p), ("types_host", ctypes.c_void_p),
                 ("box", ctypes.c_double * 9), ("pbc", ctypes.c_int * 3), ("total_charge", ctypes.c_double),
                 ("system_id", ctypes.c_long), ("E_host", ctypes.c_void_p), ("F_host", ctypes.c_void_p),
-                ("q_host", ctypes.c_void_p)]
+                ("q_host", ctypes.c_void_p), ("q0_host", ctypes.c_void_p)]
 
 
 class Result(ctypes.Structure):
@@ -69,7 +69,7 @@ class Server:
                                                    ctypes.byref(out)))
         return int(out.value)
 
-    def submit(self, pos, types, box, pbc, Q: float = 0.0, system_id: int = -1) -> int:
+    def submit(self, pos, types, box, pbc, Q: float = 0.0, system_id: int = -1, q0=None) -> int:
         pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
         n = len(pos)
         soa = np.ascontiguousarray(pos.T).reshape(-1)
@@ -89,6 +89,10 @@ class Server:
         r.total_charge = float(Q)
         r.system_id = int(system_id)
         r.E_host, r.F_host, r.q_host = E.ctypes.data, F.ctypes.data, q.ctypes.data
+        q0a = None
+        if q0 is not None:
+            q0a = np.ascontiguousarray(np.asarray(q0, dtype=np.float64).reshape(n))
+            r.q0_host = q0a.ctypes.data
         t = ctypes.c_long()
         _check(_bind().ctbop_server_submit(self.h, ctypes.byref(r), ctypes.byref(t)))
         self._out[t.value] = (E, F, q, n)
