@@ -381,6 +381,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the compact serving measurement")
     ap.add_argument("--no-fit", action="store_true", help="skip the fit-batch (parameter gradient) measurement")
     ap.add_argument("--no-removal", action="store_true", help="skip the removal-energy (desorption) measurement")
+    ap.add_argument("--no-nvt", action="store_true", help="skip the NVT (thermostatted) measurement")
+    ap.add_argument("--nvt-steps", type=int, default=50)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (scales HBM byte counters)")
     args = ap.parse_args()
@@ -519,6 +521,25 @@ def main():
         "kernels": kernels,
         "energy_change_eV_per_atom": float((thermo[1].sum() - thermo[0].sum()) / n),
     }
+    if not args.no_nvt:
+        # the paper's growth MD runs NVT at 2500 K: the same slab, continuing
+        # from the NVE state, under a Nose-Hoover chain of 3 (tau 25 fs)
+        print("bench: NVT (Nose-Hoover chain) on the same slab", file=sys.stderr, flush=True)
+        pos = x.reshape(3, n).t()
+        vel = v.reshape(3, n).t()
+        pot.md_run_nvt(pos, vel, s.types, s.box, s.pbc, 0.5, 5, T=2500.0, tau=25.0, fixed=s.fixed,
+                       thermo_every=5, sysbuf=sysb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, _, _, th, chain, info_t = pot.md_run_nvt(pos, vel, s.types, s.box, s.pbc, 0.5, args.nvt_steps,
+                                                       T=2500.0, tau=25.0, fixed=s.fixed,
+                                                       thermo_every=args.nvt_steps, sysbuf=sysb)
+        torch.cuda.synchronize()
+        tn = time.perf_counter() - t0
+        out["nvt"] = {"steps": args.nvt_steps, "atom_steps_per_s": n * args.nvt_steps / tn,
+                      "ms_per_step": tn / args.nvt_steps * 1e3, "vs_nve_step": (tn / args.nvt_steps) / (dt / args.steps),
+                      "conserved_drift_eV_per_atom": float((th[-1, 2] - th[0, 2]) / n),
+                      "thermostat": "Nose-Hoover chain M=3, tau 25 fs, target 2500 K, bottom bilayers fixed"}
     if reqs is not None:
         print("bench: compact serving measurement", file=sys.stderr, flush=True)
         del sysb

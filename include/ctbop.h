@@ -198,6 +198,28 @@ int ctbop_param_grad(ctbop_ctx *ctx, int n, const double *box_host, const int *p
                      const double *dL_dF_dev, const double *dL_dq_dev, double *grad_host, int *cg_iters,
                      void *stream);
 
+/* NVT molecular dynamics: the paper runs its growth MD in the NVT ensemble
+ * at 2500 K with the bottom of the slab fixed (growth-simulation section);
+ * the thermostat is not named, so this is a Nose-Hoover chain of chain_len
+ * (1..8) thermostats of period tau_fs on the mobile atoms at T_K kelvin,
+ * integrated by a thermostat half step, velocity Verlet and a thermostat
+ * half step (time reversible).  Arguments as for ctbop_md_run, plus:
+ *   chain_dev    double[2 * chain_len] device, in/out: the thermostat
+ *                positions xi_k then velocities vxi_k (zeros for a fresh start;
+ *                pass the returned state to continue a run)
+ *   thermo_host  NULL or 3 * (nsteps / every + 1) doubles: (E_pot, K, H) for
+ *                s = 0, every, ...; K is the kinetic energy of the mobile
+ *                atoms and H = E_pot + K + sum_k Q_k vxi_k^2 / 2 + Nf kT xi_1
+ *                + kT sum_{k>1} xi_k, the conserved quantity.
+ * Nf = 3 N_mobile, less 3 when no atom is fixed; Q_1 = Nf kT tau^2 and
+ * Q_k = kT tau^2.  E_INVAL for chain_len outside 1..8, T, tau or dt <= 0, or
+ * fewer than two mobile atoms.  Waits for the stream at the end. */
+int ctbop_md_run_nvt(ctbop_ctx *ctx, int n, double *x_dev, double *v_dev, const int32_t *types_dev,
+                     const uint8_t *fixed_dev, const double *box_host, const int *pbc_host, double total_charge,
+                     double dt_fs, int nsteps, int thermo_every, double T_K, double tau_fs, int chain_len,
+                     double *chain_dev, void *sys_dev, size_t sys_bytes, double *F_dev, double *q_dev,
+                     double *thermo_host, ctbop_info *info, void *stream);
+
 /* Device status word of `sys` (waits for the stream). */
 int ctbop_status(ctbop_ctx *ctx, void *sys_dev, size_t sys_bytes, void *stream, int *code);
 

@@ -64,6 +64,8 @@ def lib():
         L.oracle_energy_at_q.restype = c_dbl
         L.oracle_md_nve.argtypes = [c_int, _dp, _dp, _ip, _ip, _dp, _ip, _dp, c_dbl, c_dbl, c_int,
                                     c_dbl, _dp, _dp, _dp]
+        L.oracle_md_nvt.argtypes = [c_int, _dp, _dp, _ip, _ip, _dp, _ip, _dp, c_dbl, c_dbl, c_int, c_dbl, c_dbl,
+                                    c_int, _dp, _dp, c_dbl, _dp, _dp, _dp, _dp]
         L.oracle_param_derivative.argtypes = [c_int, _dp, _ip, _dp, _ip, _dp, c_dbl, c_dbl, c_int,
                                               c_dbl, _dp, _dp, _dp, _dp, _dp, _dp]
         L.oracle_threads.restype = c_int
@@ -192,6 +194,29 @@ def md_nve(pos, vel, types, fixed, box, pbc, params, dt, nsteps, Q=0.0, tol=1e-1
     if rc:
         raise RuntimeError("oracle MD: charge solve failed")
     return pos, vel, q, Et, Ep
+
+
+def md_nvt(pos, vel, types, fixed, box, pbc, params, dt, nsteps, T, tau, M=3, xi=None, vxi=None, Q=0.0,
+           tol=1e-12, q0=None):
+    """NVT by a Nose-Hoover chain of length M (thermostat period tau fs).
+    Returns (pos, vel, q, xi, vxi, Hext[nsteps+1], Epot[...], Ekin[...])."""
+    pos, types, box, pbc = _geom(pos, types, box, pbc)
+    pos = pos.copy()
+    vel = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1, 3).copy()
+    n = len(types)
+    fx = np.zeros(n, dtype=np.int32) if fixed is None else np.ascontiguousarray(fixed, dtype=np.int32)
+    q = np.zeros(n) if q0 is None else np.array(q0, dtype=np.float64, copy=True)
+    xi = np.zeros(M) if xi is None else np.array(xi, dtype=np.float64, copy=True)
+    vxi = np.zeros(M) if vxi is None else np.array(vxi, dtype=np.float64, copy=True)
+    H = np.zeros(nsteps + 1)
+    Ep = np.zeros(nsteps + 1)
+    Ek = np.zeros(nsteps + 1)
+    rc = lib().oracle_md_nvt(n, pos, vel, types, fx, box, pbc, np.ascontiguousarray(params, dtype=np.float64),
+                             float(Q), float(dt), int(nsteps), float(T), float(tau), int(M), xi, vxi, float(tol),
+                             q, H, Ep, Ek)
+    if rc:
+        raise RuntimeError("oracle NVT: charge solve failed or bad chain length")
+    return pos, vel, q, xi, vxi, H, Ep, Ek
 
 
 def param_derivative(pos, types, box, pbc, params, k, Q=0.0, tol=1e-12, h=1e-30):

@@ -639,6 +639,133 @@ int oracle_md_nve(int n, double *pos, double *vel, const int *types, const int *
     return 0;
 }
 
+/* NVT molecular dynamics with a Nose-Hoover chain thermostat.  The paper runs
+ * its growth MD in the NVT ensemble at 2500 K with the bottom of the slab fixed
+ * (growth-simulation section) without naming the thermostat; a chain of M
+ * Nose-Hoover thermostats is the stated reading.  Equations of motion, with
+ * K the kinetic energy of the mobile atoms and Nf their degrees of freedom:
+ *   dx/dt = v,   m dv/dt = F - m vxi_1 v,
+ *   Q_1 dvxi_1/dt = 2K - Nf kT - Q_1 vxi_1 vxi_2,
+ *   Q_k dvxi_k/dt = Q_{k-1} vxi_{k-1}^2 - kT - Q_k vxi_k vxi_{k+1}   (1 < k < M),
+ *   Q_M dvxi_M/dt = Q_{M-1} vxi_{M-1}^2 - kT,   dxi_k/dt = vxi_k,
+ * with Q_1 = Nf kT tau^2 and Q_k = kT tau^2.  The conserved quantity is
+ *   E_pot + K + sum_k Q_k vxi_k^2 / 2 + Nf kT xi_1 + kT sum_{k>1} xi_k.
+ * Integration: a thermostat half step, a velocity-Verlet step, a thermostat
+ * half step.  The thermostat half step (length h = dt/2) propagates the chain
+ * velocities from the last member down to the first (each force G_k applied
+ * for h/2 between two damping factors exp(-vxi_{k+1} h/4)), scales the
+ * particle velocities by exp(-vxi_1 h), advances xi_k by vxi_k h, and then
+ * repeats the chain update from the first member up to the last.  Each piece
+ * is an exact flow of part of the equations, so the step is time reversible.
+ * Nf = 3 N_mobile, less 3 when no atom is fixed (momentum is then conserved). */
+static double nhc_force(int k, int M, double K, double Nf, double kT, const double *Qm, const double *vxi)
+{
+    (void)M;
+    if (k == 0) return (2.0 * K - Nf * kT) / Qm[0];
+    return (Qm[k - 1] * vxi[k - 1] * vxi[k - 1] - kT) / Qm[k];
+}
+
+static double nhc_half_step(int M, double h, double *K, double Nf, double kT, const double *Qm, double *xi,
+                            double *vxi)
+{
+    /* down the chain */
+    vxi[M - 1] += 0.5 * h * nhc_force(M - 1, M, *K, Nf, kT, Qm, vxi);
+    for (int k = M - 2; k >= 0; k--) {
+        const double damp = exp(-0.25 * h * vxi[k + 1]);
+        vxi[k] *= damp;
+        vxi[k] += 0.5 * h * nhc_force(k, M, *K, Nf, kT, Qm, vxi);
+        vxi[k] *= damp;
+    }
+    const double scale = exp(-h * vxi[0]);
+    *K *= scale * scale;
+    for (int k = 0; k < M; k++) xi[k] += h * vxi[k];
+    /* up the chain */
+    for (int k = 0; k < M - 1; k++) {
+        const double damp = exp(-0.25 * h * vxi[k + 1]);
+        vxi[k] *= damp;
+        vxi[k] += 0.5 * h * nhc_force(k, M, *K, Nf, kT, Qm, vxi);
+        vxi[k] *= damp;
+    }
+    vxi[M - 1] += 0.5 * h * nhc_force(M - 1, M, *K, Nf, kT, Qm, vxi);
+    return scale;
+}
+
+/* Etraj[s] receives the conserved quantity, Epot[s] the potential energy and
+ * Ekin[s] the kinetic energy of the mobile atoms, s = 0..nsteps.  xi, vxi (M
+ * each) hold the chain state in and out. */
+int oracle_md_nvt(int n, double *pos, double *vel, const int *types, const int *fixed, const double *box,
+                  const int *pbc, const double *params, double Q, double dt, int nsteps, double T, double tau,
+                  int M, double *xi, double *vxi, double tol, double *q_io, double *Etraj, double *Epot,
+                  double *Ekin)
+{
+    const double acc = 9.648533212e-3;        /* (eV/Angstrom)/amu in Angstrom/fs^2 */
+    const double kB = 8.617333262e-5;         /* eV/K */
+    if (M < 1 || M > 16) return 2;
+    prm_t_r P;
+    read_params_r(params, -1, 0.0, &P);
+    int nmob = 0;
+    for (int i = 0; i < n; i++) nmob += (fixed && fixed[i]) ? 0 : 1;
+    const double Nf = 3.0 * nmob - (nmob == n ? 3.0 : 0.0);
+    const double kT = kB * T;
+    double Qm[16];
+    for (int k = 0; k < M; k++) Qm[k] = (k == 0 ? Nf : 1.0) * kT * tau * tau;
+    double *F = malloc(sizeof(double) * 3 * n), E;
+    double info[5];
+    if (oracle_eval(n, pos, types, box, pbc, params, Q, tol, 2000, -1, q_io, &E, F, NULL, info)) {
+        free(F);
+        return 1;
+    }
+    for (int s = 0; s <= nsteps; s++) {
+        if (s > 0) {
+            double K = 0.0;
+            for (int i = 0; i < n; i++) {
+                if (fixed && fixed[i]) continue;
+                const double m = P.sp[types[i]].mass;
+                for (int a = 0; a < 3; a++) K += 0.5 * m * vel[3 * i + a] * vel[3 * i + a] / acc;
+            }
+            double sc = nhc_half_step(M, 0.5 * dt, &K, Nf, kT, Qm, xi, vxi);
+            for (int i = 0; i < n; i++) {
+                if (fixed && fixed[i]) continue;
+                const double m = P.sp[types[i]].mass;
+                for (int a = 0; a < 3; a++) {
+                    vel[3 * i + a] = sc * vel[3 * i + a] + 0.5 * dt * acc * F[3 * i + a] / m;
+                    pos[3 * i + a] += dt * vel[3 * i + a];
+                }
+            }
+            if (oracle_eval(n, pos, types, box, pbc, params, Q, tol, 2000, -1, q_io, &E, F, NULL, info)) {
+                free(F);
+                return 1;
+            }
+            K = 0.0;
+            for (int i = 0; i < n; i++) {
+                if (fixed && fixed[i]) continue;
+                const double m = P.sp[types[i]].mass;
+                for (int a = 0; a < 3; a++) {
+                    vel[3 * i + a] += 0.5 * dt * acc * F[3 * i + a] / m;
+                    K += 0.5 * m * vel[3 * i + a] * vel[3 * i + a] / acc;
+                }
+            }
+            sc = nhc_half_step(M, 0.5 * dt, &K, Nf, kT, Qm, xi, vxi);
+            for (int i = 0; i < n; i++) {
+                if (fixed && fixed[i]) continue;
+                for (int a = 0; a < 3; a++) vel[3 * i + a] *= sc;
+            }
+        }
+        double K = 0.0, Eth = Nf * kT * xi[0];
+        for (int i = 0; i < n; i++) {
+            if (fixed && fixed[i]) continue;
+            const double m = P.sp[types[i]].mass;
+            for (int a = 0; a < 3; a++) K += 0.5 * m * vel[3 * i + a] * vel[3 * i + a] / acc;
+        }
+        for (int k = 0; k < M; k++) Eth += 0.5 * Qm[k] * vxi[k] * vxi[k] + (k > 0 ? kT * xi[k] : 0.0);
+        if (Etraj) Etraj[s] = E + K + Eth;
+        if (Epot) Epot[s] = E;
+        if (Ekin) Ekin[s] = K;
+    }
+    free(F);
+    return 0;
+}
+
 /* Parameter derivatives by complex step: for parameter k, dE/dtheta_k,
  * dF/dtheta_k (n x 3) and dq/dtheta_k (n), all at the equilibrated charges
  * (the charge solve is redone in complex arithmetic, so the charges' response

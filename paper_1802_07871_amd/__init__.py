@@ -55,7 +55,7 @@ _lib = None
 EXPORTS = ("ctbop_default_opts", "ctbop_create", "ctbop_destroy", "ctbop_system_bytes",
            "ctbop_compute_energy_forces_charges", "ctbop_md_run", "ctbop_status", "ctbop_last_error",
            "ctbop_debug_lists", "ctbop_profile", "ctbop_set_params", "ctbop_param_grad_bytes", "ctbop_param_grad",
-           "ctbop_removal_bytes", "ctbop_removal_energies")
+           "ctbop_removal_bytes", "ctbop_removal_energies", "ctbop_md_run_nvt")
 
 
 def lib():
@@ -82,6 +82,8 @@ def lib():
         L.ctbop_param_grad_bytes.argtypes = [vp, i32, vp, vp, ctypes.POINTER(sz)]
         L.ctbop_param_grad.argtypes = [vp, i32, vp, vp, vp, sz, vp, sz, dbl, vp, vp, vp, ctypes.POINTER(i32), vp]
         L.ctbop_removal_bytes.argtypes = [vp, i32, vp, vp, i32, ctypes.POINTER(sz)]
+        L.ctbop_md_run_nvt.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, dbl, dbl, i32, i32, dbl, dbl, i32, vp, vp,
+                                       sz, vp, vp, vp, ctypes.POINTER(Info), vp]
         L.ctbop_removal_energies.argtypes = [vp, i32, vp, vp, vp, vp, dbl, vp, i32, vp, sz, vp, vp, vp, vp]
         _lib = L
     return _lib
@@ -260,6 +262,41 @@ class Potential:
         _check(rc)
         return (x.reshape(3, n).t().contiguous(), v.reshape(3, n).t().contiguous(),
                 F.reshape(3, n).t().contiguous(), q, thermo, info.as_dict())
+
+    def md_run_nvt(self, pos, vel, types, box, pbc, dt, nsteps, T, tau, chain_len=3, chain=None, fixed=None,
+                   Q=0.0, thermo_every=1, sysbuf=None):
+        """Nose-Hoover-chain NVT on the device.  pos, vel (n,3).  chain: None
+        (fresh) or the 2*chain_len state returned by a previous call.  Returns
+        (pos, vel, F, q, thermo (k,3) numpy [E_pot, K, H], chain, info)."""
+        torch = _torch()
+        pos = torch.as_tensor(pos, dtype=torch.float64, device="cuda").reshape(-1, 3)
+        vel = torch.as_tensor(vel, dtype=torch.float64, device="cuda").reshape(-1, 3)
+        types = torch.as_tensor(types, dtype=torch.int32, device="cuda").contiguous()
+        n = types.shape[0]
+        x = pos.t().contiguous().reshape(-1)
+        v = vel.t().contiguous().reshape(-1)
+        F = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+        q = torch.empty(n, dtype=torch.float64, device="cuda")
+        ch = torch.zeros(2 * chain_len, dtype=torch.float64, device="cuda") if chain is None else \
+            torch.as_tensor(np.asarray(chain, dtype=np.float64), device="cuda").contiguous()
+        fx = None
+        if fixed is not None:
+            fx = torch.as_tensor(np.asarray(fixed, dtype=np.uint8), device="cuda").contiguous()
+        s = self._sys_for(n, box, pbc, sysbuf)
+        b, p = _box_pbc(box, pbc)
+        every = max(1, int(thermo_every))
+        thermo = np.zeros((nsteps // every + 1, 3))
+        info = Info()
+        rc = lib().ctbop_md_run_nvt(self.ctx, int(n), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(v.data_ptr()),
+                                    ctypes.c_void_p(types.data_ptr()),
+                                    ctypes.c_void_p(fx.data_ptr()) if fx is not None else None,
+                                    b.ctypes.data, p.ctypes.data, float(Q), float(dt), int(nsteps), every, float(T),
+                                    float(tau), int(chain_len), ctypes.c_void_p(ch.data_ptr()), s.ptr(), s.nbytes,
+                                    ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(q.data_ptr()), thermo.ctypes.data,
+                                    ctypes.byref(info), _stream())
+        _check(rc)
+        return (x.reshape(3, n).t().contiguous(), v.reshape(3, n).t().contiguous(),
+                F.reshape(3, n).t().contiguous(), q, thermo, ch.cpu().numpy(), info.as_dict())
 
     def removal_energies(self, pos, types, box, pbc, candidates, Q=0.0, concurrency: int = 16):
         """dE_i = E(X without atom i) - E(X) for every candidate i, charges

@@ -209,7 +209,7 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
     L.off_sst = take(sizeof(SegState));
     L.off_tiles = take(sizeof(Tile) * S.ntile);
     L.off_segid = take(sizeof(int));
-    L.off_ke = take(2 * sizeof(double));
+    L.off_ke = take(8 * sizeof(double));
     size_t o_perm = take(4 * np), o_cellof = take(4 * (size_t)n), o_csort = take(4 * np);
     size_t o_cs = take(4 * ((size_t)S.ncell + 1)), o_cc = take(4 * (size_t)S.ncell);
     size_t o_off = take(8 * 3 * np), o_ref = take(8 * 3 * (size_t)n), o_xs = take(v4 * np);
@@ -707,6 +707,94 @@ int ctbop_md_run(ctbop_ctx *ctx, int n, double *x, double *v, const int32_t *typ
         }
     }
     (void)status_acc;
+    if (info) return fill_info(ctx, P, info);
+    HIPCHK(hipStreamSynchronize(P.st));
+    return CTBOP_OK;
+}
+
+int ctbop_md_run_nvt(ctbop_ctx *ctx, int n, double *x, double *v, const int32_t *types, const uint8_t *fixed,
+                     const double *box, const int *pbc, double Q, double dt, int nsteps, int every, double T_K,
+                     double tau_fs, int chain_len, double *chain, void *sys, size_t sys_bytes, double *F, double *q,
+                     double *thermo, ctbop_info *info, void *stream)
+{
+    if (!x || !v || !types || !F || !q || !chain || nsteps < 0) return fail(CTBOP_E_INVAL, "bad argument");
+    if (chain_len < 1 || chain_len > NHC_MAX) return fail(CTBOP_E_INVAL, "chain length must be 1..8");
+    if (!(T_K > 0) || !(tau_fs > 0) || !(dt > 0)) return fail(CTBOP_E_INVAL, "need T, tau, dt > 0");
+    if (every <= 0) every = 1;
+    Prep P;
+    int rc = prepare(ctx, n, box, pbc, sys, sys_bytes, stream, P);
+    if (rc) return rc;
+    Seg S = P.L.seg;
+    S.x = x;
+    S.type = types;
+    S.F = F;
+    S.q_out = q;
+    S.E_out = nullptr;
+    S.Q = Q;
+    hipLaunchKernelGGL(k_set_seg, dim3(1), dim3(1), 0, P.st, P.dseg, S);
+    const dim3 g(P.L.ntile), b(TILE), g1(1);
+    // degrees of freedom of the mobile atoms (momentum conserved only if none is fixed)
+    hipLaunchKernelGGL(k_count_fixed, g, b, 0, P.st, P.dtiles, P.dseg, fixed);
+    hipLaunchKernelGGL(k_fin_ke, g1, b, 0, P.st, P.dsegid, P.dseg, P.dke + 6);
+    double nfix = 0.0;
+    HIPCHK(hipMemcpyAsync(&nfix, P.dke + 6, sizeof(double), hipMemcpyDeviceToHost, P.st));
+    HIPCHK(hipStreamSynchronize(P.st));
+    const int nmob = n - (int)llround(nfix);
+    if (nmob < 2) return fail(CTBOP_E_INVAL, "NVT needs at least two mobile atoms");
+    NhcCfg c;
+    memset(&c, 0, sizeof c);
+    c.M = chain_len;
+    c.dt = dt;
+    c.kT = 8.617333262e-5 * T_K;
+    c.Nf = 3.0 * nmob - (nmob == n ? 3.0 : 0.0);
+    for (int k = 0; k < chain_len; k++) c.Qm[k] = (k == 0 ? c.Nf : 1.0) * c.kT * tau_fs * tau_fs;
+    MdIO io;
+    io.x = x;
+    io.v = v;
+    io.F = F;
+    io.fixed = fixed;
+    io.dt = dt;
+    io.mass[0] = ctx->theta[25];
+    io.mass[1] = ctx->theta[26 + 25];
+    io.vscale = P.dke + 2;
+    io.ke_mobile = 1;
+    MdIO io0 = io;
+    io0.dt = 0.0;
+    int iters = 0;
+    const int mdflags = CTBOP_FLAG_WARM_START | CTBOP_FLAG_EXTRAPOLATE;
+    rc = eval_any(ctx, P, mdflags, &iters);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_md_kick, g, b, 0, P.st, P.dtiles, P.dseg, io0);
+    hipLaunchKernelGGL(k_fin_ke, g1, b, 0, P.st, P.dsegid, P.dseg, P.dke);
+    hipLaunchKernelGGL(k_nhc, g1, dim3(64), 0, P.st, P.dke, chain, c, nsteps > 0 ? 0 : 3);
+    for (int s = 0; s <= nsteps; s++) {
+        if (s > 0) {
+            hipLaunchKernelGGL(k_md_kick_drift, g, b, 0, P.st, P.dtiles, P.dseg, io);
+            rc = eval_any(ctx, P, mdflags, &iters);
+            if (rc) return rc;
+            hipLaunchKernelGGL(k_md_kick, g, b, 0, P.st, P.dtiles, P.dseg, io);
+            hipLaunchKernelGGL(k_fin_ke, g1, b, 0, P.st, P.dsegid, P.dseg, P.dke);
+            hipLaunchKernelGGL(k_nhc, g1, dim3(64), 0, P.st, P.dke, chain, c, s < nsteps ? 1 : 2);
+            HIPCHK(hipGetLastError());
+        }
+        if (thermo && s % every == 0) {
+            double kv[5];
+            HIPCHK(hipMemcpyAsync(kv, P.dke, sizeof kv, hipMemcpyDeviceToHost, P.st));
+            HIPCHK(hipStreamSynchronize(P.st));
+            thermo[3 * (s / every)] = kv[1];
+            thermo[3 * (s / every) + 1] = kv[3];
+            thermo[3 * (s / every) + 2] = kv[1] + kv[3] + kv[4];
+        }
+        if (s % 64 == 0 || s == nsteps) {
+            int code = 0;
+            HIPCHK(hipMemcpyAsync(&code, &P.L.seg.sst->status, sizeof(int), hipMemcpyDeviceToHost, P.st));
+            HIPCHK(hipStreamSynchronize(P.st));
+            if (code) return fail(map_status(code), status_text(code));
+        }
+    }
+    // the last thermostat half step's scale
+    if (nsteps > 0) hipLaunchKernelGGL(k_md_scale, g, b, 0, P.st, P.dtiles, P.dseg, io);
+    HIPCHK(hipGetLastError());
     if (info) return fill_info(ctx, P, info);
     HIPCHK(hipStreamSynchronize(P.st));
     return CTBOP_OK;

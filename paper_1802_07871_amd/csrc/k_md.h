@@ -1,4 +1,5 @@
-// k_md.h -- velocity-Verlet NVE integration (user atom order).
+// k_md.h -- velocity-Verlet integration (user atom order), NVE or NVT with a
+// Nose-Hoover chain thermostat.
 //
 // Half kick + drift before the force evaluation, half kick after it.  Atoms
 // with a nonzero fixed flag neither move nor change velocity (the paper holds
@@ -16,6 +17,8 @@ struct MdIO {
     const uint8_t *fixed;
     double dt;
     double mass[2];
+    const double *vscale = nullptr;   // NVT: thermostat scaling of the mobile velocities before the kick
+    int ke_mobile = 0;                // kinetic energy of the mobile atoms only
 };
 
 __global__ void __launch_bounds__(TILE) k_md_kick_drift(const Tile *tiles, Seg *segs, MdIO io)
@@ -26,9 +29,10 @@ __global__ void __launch_bounds__(TILE) k_md_kick_drift(const Tile *tiles, Seg *
     if (i >= S.n) return;
     if (io.fixed && io.fixed[i]) return;
     const double a = 0.5 * io.dt * ACC_UNIT / io.mass[S.type[i]];
+    const double sc = io.vscale ? *io.vscale : 1.0;
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        const double v = io.v[d * S.n + i] + a * io.F[d * S.n + i];
+        const double v = sc * io.v[d * S.n + i] + a * io.F[d * S.n + i];
         io.v[d * S.n + i] = v;
         io.x[d * S.n + i] += io.dt * v;
     }
@@ -53,7 +57,7 @@ __global__ void __launch_bounds__(TILE) k_md_kick(const Tile *tiles, Seg *segs, 
                 v += a * io.F[d * S.n + i];
                 io.v[d * S.n + i] = v;
             }
-            ke += 0.5 * m * v * v / ACC_UNIT;
+            if (mob || !io.ke_mobile) ke += 0.5 * m * v * v / ACC_UNIT;
         }
     }
     double v1[1] = {ke};
@@ -71,6 +75,95 @@ __global__ void k_fin_ke(const int *seg_ids, Seg *segs, double *ke_out)
         ke_out[0] = tot[0];
         ke_out[1] = S.sst->energy;
     }
+}
+
+// ---------------------------------------------------------------------------
+// NVT: Nose-Hoover chain of M thermostats on the mobile atoms.  With K their
+// kinetic energy and Nf their degrees of freedom,
+//   m dv/dt = F - m vxi_1 v,   Q_1 dvxi_1/dt = 2K - Nf kT - Q_1 vxi_1 vxi_2,
+//   Q_k dvxi_k/dt = Q_{k-1} vxi_{k-1}^2 - kT - Q_k vxi_k vxi_{k+1},  dxi_k/dt = vxi_k,
+// Q_1 = Nf kT tau^2, Q_k = kT tau^2; conserved: E_pot + K + sum Q_k vxi_k^2/2
+// + Nf kT xi_1 + kT sum_{k>1} xi_k.  A step is a thermostat half step, velocity
+// Verlet and a thermostat half step; the half step propagates the chain
+// velocities from the last member to the first, scales the particle
+// velocities by exp(-vxi_1 dt/2), advances the xi, and propagates the chain
+// back up (the split flows are exact, so the step is time reversible).
+// ---------------------------------------------------------------------------
+constexpr int NHC_MAX = 8;
+struct NhcCfg {
+    int M;
+    double dt, kT, Nf;
+    double Qm[NHC_MAX];
+};
+
+__device__ double nhc_g(const NhcCfg &c, int k, double K, const double *vxi)
+{
+    return k == 0 ? (2.0 * K - c.Nf * c.kT) / c.Qm[0] : (c.Qm[k - 1] * vxi[k - 1] * vxi[k - 1] - c.kT) / c.Qm[k];
+}
+
+// one thermostat half step (length dt/2); K is scaled with the velocities,
+// the returned factor applies to the mobile velocities
+__device__ double nhc_half(const NhcCfg &c, double &K, double *xi, double *vxi)
+{
+    const double h = 0.5 * c.dt;
+    const int M = c.M;
+    vxi[M - 1] += 0.5 * h * nhc_g(c, M - 1, K, vxi);
+    for (int k = M - 2; k >= 0; k--) {
+        const double damp = exp(-0.25 * h * vxi[k + 1]);
+        vxi[k] = (vxi[k] * damp + 0.5 * h * nhc_g(c, k, K, vxi)) * damp;
+    }
+    const double sc = exp(-h * vxi[0]);
+    K *= sc * sc;
+    for (int k = 0; k < M; k++) xi[k] += h * vxi[k];
+    for (int k = 0; k < M - 1; k++) {
+        const double damp = exp(-0.25 * h * vxi[k + 1]);
+        vxi[k] = (vxi[k] * damp + 0.5 * h * nhc_g(c, k, K, vxi)) * damp;
+    }
+    vxi[M - 1] += 0.5 * h * nhc_g(c, M - 1, K, vxi);
+    return sc;
+}
+
+// One thread.  ke[0] holds K after the step's second half kick (or of the
+// initial velocities).  mode 0: start (first half step of the next step only);
+// 1: end of a step (second half step) and the next step's first half step;
+// 2: end of the last step; 3: report only.  Writes ke[2] = the velocity scale
+// still to apply (by the next kick-drift, or by k_md_scale after the last
+// step), ke[3] = K of the step's final velocities, ke[4] = the chain's energy.
+__global__ void k_nhc(double *ke, double *chain, NhcCfg c, int mode)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double *xi = chain, *vxi = chain + c.M;
+    double K = ke[0], scale = 1.0;
+    if (mode == 1 || mode == 2) scale = nhc_half(c, K, xi, vxi);
+    double eth = c.Nf * c.kT * xi[0];
+    for (int k = 0; k < c.M; k++) eth += 0.5 * c.Qm[k] * vxi[k] * vxi[k] + (k > 0 ? c.kT * xi[k] : 0.0);
+    ke[3] = K;
+    ke[4] = eth;
+    if (mode == 0 || mode == 1) scale *= nhc_half(c, K, xi, vxi);
+    ke[2] = scale;
+}
+
+// apply the pending thermostat scale to the mobile velocities
+__global__ void __launch_bounds__(TILE) k_md_scale(const Tile *tiles, Seg *segs, MdIO io)
+{
+    const Tile T = my_tile(tiles);
+    const Seg &S = segs[T.seg];
+    const int i = T.row0 + threadIdx.x;
+    if (i >= S.n || (io.fixed && io.fixed[i])) return;
+    const double sc = *io.vscale;
+#pragma unroll
+    for (int d = 0; d < 3; d++) io.v[d * S.n + i] *= sc;
+}
+
+// number of fixed atoms (tile partials)
+__global__ void __launch_bounds__(TILE) k_count_fixed(const Tile *tiles, Seg *segs, const uint8_t *fixed)
+{
+    const Tile T = my_tile(tiles);
+    const Seg &S = segs[T.seg];
+    __shared__ double lds[4];
+    const int i = T.row0 + threadIdx.x;
+    double v[1] = {(i < S.n && fixed && fixed[i]) ? 1.0 : 0.0};
+    tile_partials<1>(S, T.row0 / TILE, v, lds);
 }
 
 } // namespace ctbop
