@@ -383,6 +383,8 @@ def main():
     ap.add_argument("--no-removal", action="store_true", help="skip the removal-energy (desorption) measurement")
     ap.add_argument("--no-nvt", action="store_true", help="skip the NVT (thermostatted) measurement")
     ap.add_argument("--nvt-steps", type=int, default=50)
+    ap.add_argument("--no-relax", action="store_true", help="skip the FIRE relaxation measurement")
+    ap.add_argument("--relax-steps", type=int, default=100)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (scales HBM byte counters)")
     args = ap.parse_args()
@@ -531,7 +533,7 @@ def main():
                        thermo_every=5, sysbuf=sysb)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, _, _, _, th, chain, info_t = pot.md_run_nvt(pos, vel, s.types, s.box, s.pbc, 0.5, args.nvt_steps,
+        pos, _, _, _, th, chain, info_t = pot.md_run_nvt(pos, vel, s.types, s.box, s.pbc, 0.5, args.nvt_steps,
                                                        T=2500.0, tau=25.0, fixed=s.fixed,
                                                        thermo_every=args.nvt_steps, sysbuf=sysb)
         torch.cuda.synchronize()
@@ -540,6 +542,21 @@ def main():
                       "ms_per_step": tn / args.nvt_steps * 1e3, "vs_nve_step": (tn / args.nvt_steps) / (dt / args.steps),
                       "conserved_drift_eV_per_atom": float((th[-1, 2] - th[0, 2]) / n),
                       "thermostat": "Nose-Hoover chain M=3, tau 25 fs, target 2500 K, bottom bilayers fixed"}
+    if not args.no_relax:
+        # quench: FIRE relaxation of the hot slab (the paper relaxes its
+        # structures after the anneal), a fixed number of iterations
+        print("bench: FIRE relaxation of the hot slab", file=sys.stderr, flush=True)
+        pos = pos if not args.no_nvt else x.reshape(3, n).t()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, _, Et, k, fm, conv, info_r = pot.relax_fire(pos, s.types, s.box, s.pbc, fmax=1e-3,
+                                                          max_steps=args.relax_steps, fixed=s.fixed, sysbuf=sysb)
+        torch.cuda.synchronize()
+        tr = time.perf_counter() - t0
+        out["relax"] = {"steps": k, "atom_steps_per_s": n * k / tr, "ms_per_step": tr / max(k, 1) * 1e3,
+                        "energy_drop_eV_per_atom": float((Et[0] - Et[-1]) / n), "fmax_end_eV_per_A": fm,
+                        "converged": conv,
+                        "minimiser": "FIRE (published constants), dt0 0.5 fs, dtmax 5 fs, bottom bilayers fixed"}
     if reqs is not None:
         print("bench: compact serving measurement", file=sys.stderr, flush=True)
         del sysb

@@ -220,6 +220,32 @@ int ctbop_md_run_nvt(ctbop_ctx *ctx, int n, double *x_dev, double *v_dev, const 
                      double *chain_dev, void *sys_dev, size_t sys_bytes, double *F_dev, double *q_dev,
                      double *thermo_host, ctbop_info *info, void *stream);
 
+/* Structure relaxation at fixed cell: the paper relaxes its graphene-on-SiC
+ * structures and annealed samples (graphene and anneal sections) without
+ * naming the minimiser; this is FIRE (Bitzek et al., Phys. Rev. Lett. 97,
+ * 170201, 2006) with its published constants (n_min 5, f_inc 1.1, f_dec 0.5,
+ * alpha_start 0.1, f_alpha 0.99).  From rest with step dt0_fs, each iteration
+ * is one velocity-Verlet step with the atoms' masses; then, unless the
+ * largest force on a mobile atom is below fmax (eV/Angstrom), with P = F.v:
+ * v <- (1 - alpha) v + alpha |v| F/|F|; if P > 0, after more than n_min
+ * such steps in a row dt <- min(f_inc dt, dtmax_fs) and alpha <- f_alpha
+ * alpha; if P <= 0, dt <- f_dec dt, v <- 0, alpha <- alpha_start.  Fixed
+ * atoms (fixed_dev != 0) neither move nor count.  Charges are re-equilibrated
+ * at every step (warm start, no time extrapolation).
+ *   x_dev        double[3n] SoA positions (device, in/out)
+ *   v_dev        double[3n] device velocity workspace (zeroed on entry)
+ *   E_trace_host NULL or max_steps + 1 doubles: the energy after step s
+ *   steps_out    iterations taken; fmax_out the final largest force;
+ *   converged    1 if it fell below fmax, 0 if max_steps ran out
+ * F_dev, q_dev receive the final forces and charges.  E_INVAL for fmax <= 0,
+ * dt0 <= 0 or dtmax < dt0; the solver codes of the evaluation otherwise.
+ * Reads four reductions back after every step (waits for the stream). */
+int ctbop_relax_fire(ctbop_ctx *ctx, int n, double *x_dev, double *v_dev, const int32_t *types_dev,
+                     const uint8_t *fixed_dev, const double *box_host, const int *pbc_host, double total_charge,
+                     double fmax, int max_steps, double dt0_fs, double dtmax_fs, void *sys_dev, size_t sys_bytes,
+                     double *F_dev, double *q_dev, double *E_trace_host, int *steps_out, double *fmax_out,
+                     int *converged, ctbop_info *info, void *stream);
+
 /* Device status word of `sys` (waits for the stream). */
 int ctbop_status(ctbop_ctx *ctx, void *sys_dev, size_t sys_bytes, void *stream, int *code);
 

@@ -66,6 +66,9 @@ def lib():
                                     c_dbl, _dp, _dp, _dp]
         L.oracle_md_nvt.argtypes = [c_int, _dp, _dp, _ip, _ip, _dp, _ip, _dp, c_dbl, c_dbl, c_int, c_dbl, c_dbl,
                                     c_int, _dp, _dp, c_dbl, _dp, _dp, _dp, _dp]
+        _ipp = ctypes.POINTER(c_int)
+        L.oracle_relax_fire.argtypes = [c_int, _dp, _ip, _ip, _dp, _ip, _dp, c_dbl, c_dbl, c_int, c_dbl, c_dbl,
+                                        c_dbl, _dp, ctypes.c_void_p, _ipp, ctypes.POINTER(c_dbl), _ipp]
         L.oracle_param_derivative.argtypes = [c_int, _dp, _ip, _dp, _ip, _dp, c_dbl, c_dbl, c_int,
                                               c_dbl, _dp, _dp, _dp, _dp, _dp, _dp]
         L.oracle_threads.restype = c_int
@@ -217,6 +220,25 @@ def md_nvt(pos, vel, types, fixed, box, pbc, params, dt, nsteps, T, tau, M=3, xi
     if rc:
         raise RuntimeError("oracle NVT: charge solve failed or bad chain length")
     return pos, vel, q, xi, vxi, H, Ep, Ek
+
+
+def relax_fire(pos, types, fixed, box, pbc, params, fmax, max_steps, dt0=0.5, dtmax=5.0, Q=0.0, tol=1e-12):
+    """FIRE relaxation (the published algorithm and constants) until the
+    largest force on a mobile atom is below fmax eV/A or max_steps MD steps.
+    Returns (pos, q, E trace [steps+1], steps, final max force, converged)."""
+    pos, types, box, pbc = _geom(pos, types, box, pbc)
+    pos = pos.copy()
+    n = len(types)
+    fx = np.zeros(n, dtype=np.int32) if fixed is None else np.ascontiguousarray(fixed, dtype=np.int32)
+    q = np.zeros(n)
+    Et = np.zeros(max_steps + 1)
+    steps, fm, conv = ctypes.c_int(), ctypes.c_double(), ctypes.c_int()
+    rc = lib().oracle_relax_fire(n, pos, types, fx, box, pbc, np.ascontiguousarray(params, dtype=np.float64),
+                                 float(Q), float(fmax), int(max_steps), float(dt0), float(dtmax), float(tol), q,
+                                 Et.ctypes.data, ctypes.byref(steps), ctypes.byref(fm), ctypes.byref(conv))
+    if rc:
+        raise RuntimeError("oracle FIRE: charge solve failed")
+    return pos, q, Et[:steps.value + 1], steps.value, fm.value, bool(conv.value)
 
 
 def param_derivative(pos, types, box, pbc, params, k, Q=0.0, tol=1e-12, h=1e-30):

@@ -766,6 +766,112 @@ int oracle_md_nvt(int n, double *pos, double *vel, const int *types, const int *
     return 0;
 }
 
+/* Structure relaxation by FIRE (Bitzek, Koskinen, Gaehler, Moseler and
+ * Gumbsch, Phys. Rev. Lett. 97, 170201 (2006)).  The paper relaxes its
+ * graphene-on-SiC structures and annealed samples without naming the
+ * minimiser; FIRE is the stated reading.  Starting from rest with step dt0,
+ * mixing alpha_start and a count of uphill-free steps n_pos = 0, each
+ * iteration takes one velocity-Verlet step of length dt with the atoms' own
+ * masses, stops when the largest force on a mobile atom is below fmax, and
+ * otherwise, with P = F.v and norms |v|, |F| over all mobile components:
+ *   v <- (1 - alpha) v + alpha |v| F / |F|;
+ *   P > 0:  n_pos += 1, and once n_pos > n_min:  dt <- min(f_inc dt, dtmax),
+ *           alpha <- f_alpha alpha;
+ *   P <= 0: dt <- f_dec dt, v <- 0, alpha <- alpha_start, n_pos <- 0.
+ * n_min = 5, f_inc = 1.1, f_dec = 0.5, alpha_start = 0.1, f_alpha = 0.99 (the
+ * published values).  Fixed atoms neither move nor enter P, the norms or the
+ * convergence test.  Etrace[s] (s = 0..steps, may be NULL; room for
+ * max_steps + 1) gets the energy after step s.  Returns 0 and sets *steps
+ * (iterations taken), *fmax_out and *converged; 1 if a charge solve fails. */
+int oracle_relax_fire(int n, double *pos, const int *types, const int *fixed, const double *box, const int *pbc,
+                      const double *params, double Q, double fmax, int max_steps, double dt0, double dtmax,
+                      double tol, double *q_io, double *Etrace, int *steps, double *fmax_out, int *converged)
+{
+    const double acc = 9.648533212e-3;        /* (eV/Angstrom)/amu in Angstrom/fs^2 */
+    const int n_min = 5;
+    const double f_inc = 1.1, f_dec = 0.5, alpha_start = 0.1, f_alpha = 0.99;
+    prm_t_r P;
+    read_params_r(params, -1, 0.0, &P);
+    double *F = malloc(sizeof(double) * 3 * n), *vel = calloc(3 * n, sizeof(double)), E;
+    double info[5];
+    double dt = dt0, alpha = alpha_start;
+    int n_pos = 0, s = 0;
+    *converged = 0;
+    if (oracle_eval(n, pos, types, box, pbc, params, Q, tol, 2000, -1, q_io, &E, F, NULL, info)) {
+        free(F);
+        free(vel);
+        return 1;
+    }
+    for (;;) {
+        double fm2 = 0.0;
+        for (int i = 0; i < n; i++) {
+            if (fixed && fixed[i]) continue;
+            const double f2 = F[3 * i] * F[3 * i] + F[3 * i + 1] * F[3 * i + 1] + F[3 * i + 2] * F[3 * i + 2];
+            if (f2 > fm2) fm2 = f2;
+        }
+        if (Etrace) Etrace[s] = E;
+        *fmax_out = sqrt(fm2);
+        if (*fmax_out < fmax) {
+            *converged = 1;
+            break;
+        }
+        if (s == max_steps) break;
+        if (s > 0) {
+            /* F1-F4 on the state after the last MD step */
+            double Pw = 0.0, vv = 0.0, ff = 0.0;
+            for (int i = 0; i < n; i++) {
+                if (fixed && fixed[i]) continue;
+                for (int a = 0; a < 3; a++) {
+                    Pw += F[3 * i + a] * vel[3 * i + a];
+                    vv += vel[3 * i + a] * vel[3 * i + a];
+                    ff += F[3 * i + a] * F[3 * i + a];
+                }
+            }
+            const double c = ff > 0.0 ? alpha * sqrt(vv) / sqrt(ff) : 0.0;
+            for (int i = 0; i < n; i++) {
+                if (fixed && fixed[i]) continue;
+                for (int a = 0; a < 3; a++) vel[3 * i + a] = (1.0 - alpha) * vel[3 * i + a] + c * F[3 * i + a];
+            }
+            if (Pw > 0.0) {
+                n_pos++;
+                if (n_pos > n_min) {
+                    dt = fmin(dt * f_inc, dtmax);
+                    alpha *= f_alpha;
+                }
+            } else {
+                dt *= f_dec;
+                for (int k = 0; k < 3 * n; k++) vel[k] = 0.0;
+                alpha = alpha_start;
+                n_pos = 0;
+            }
+        }
+        /* MD step */
+        for (int i = 0; i < n; i++) {
+            if (fixed && fixed[i]) continue;
+            const double m = P.sp[types[i]].mass;
+            for (int a = 0; a < 3; a++) {
+                vel[3 * i + a] += 0.5 * dt * acc * F[3 * i + a] / m;
+                pos[3 * i + a] += dt * vel[3 * i + a];
+            }
+        }
+        if (oracle_eval(n, pos, types, box, pbc, params, Q, tol, 2000, -1, q_io, &E, F, NULL, info)) {
+            free(F);
+            free(vel);
+            return 1;
+        }
+        for (int i = 0; i < n; i++) {
+            if (fixed && fixed[i]) continue;
+            const double m = P.sp[types[i]].mass;
+            for (int a = 0; a < 3; a++) vel[3 * i + a] += 0.5 * dt * acc * F[3 * i + a] / m;
+        }
+        s++;
+    }
+    *steps = s;
+    free(F);
+    free(vel);
+    return 0;
+}
+
 /* Parameter derivatives by complex step: for parameter k, dE/dtheta_k,
  * dF/dtheta_k (n x 3) and dq/dtheta_k (n), all at the equilibrated charges
  * (the charge solve is redone in complex arithmetic, so the charges' response

@@ -55,7 +55,7 @@ _lib = None
 EXPORTS = ("ctbop_default_opts", "ctbop_create", "ctbop_destroy", "ctbop_system_bytes",
            "ctbop_compute_energy_forces_charges", "ctbop_md_run", "ctbop_status", "ctbop_last_error",
            "ctbop_debug_lists", "ctbop_profile", "ctbop_set_params", "ctbop_param_grad_bytes", "ctbop_param_grad",
-           "ctbop_removal_bytes", "ctbop_removal_energies", "ctbop_md_run_nvt")
+           "ctbop_removal_bytes", "ctbop_removal_energies", "ctbop_md_run_nvt", "ctbop_relax_fire")
 
 
 def lib():
@@ -84,6 +84,9 @@ def lib():
         L.ctbop_removal_bytes.argtypes = [vp, i32, vp, vp, i32, ctypes.POINTER(sz)]
         L.ctbop_md_run_nvt.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, dbl, dbl, i32, i32, dbl, dbl, i32, vp, vp,
                                        sz, vp, vp, vp, ctypes.POINTER(Info), vp]
+        L.ctbop_relax_fire.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, dbl, dbl, i32, dbl, dbl, vp, sz, vp, vp, vp,
+                                       ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.POINTER(i32),
+                                       ctypes.POINTER(Info), vp]
         L.ctbop_removal_energies.argtypes = [vp, i32, vp, vp, vp, vp, dbl, vp, i32, vp, sz, vp, vp, vp, vp]
         _lib = L
     return _lib
@@ -297,6 +300,39 @@ class Potential:
         _check(rc)
         return (x.reshape(3, n).t().contiguous(), v.reshape(3, n).t().contiguous(),
                 F.reshape(3, n).t().contiguous(), q, thermo, ch.cpu().numpy(), info.as_dict())
+
+    def relax_fire(self, pos, types, box, pbc, fmax=1e-3, max_steps=1000, dt0=0.5, dtmax=5.0, fixed=None, Q=0.0,
+                   sysbuf=None):
+        """FIRE relaxation at fixed cell until the largest force on a mobile
+        atom is below fmax (eV/A) or max_steps steps.  pos (n,3).  Returns
+        (pos (n,3), F (n,3), q, E trace numpy [steps+1], steps, final max
+        force, converged, info)."""
+        torch = _torch()
+        pos = torch.as_tensor(pos, dtype=torch.float64, device="cuda").reshape(-1, 3)
+        types = torch.as_tensor(types, dtype=torch.int32, device="cuda").contiguous()
+        n = types.shape[0]
+        x = pos.t().contiguous().reshape(-1)
+        v = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+        F = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+        q = torch.empty(n, dtype=torch.float64, device="cuda")
+        fx = None
+        if fixed is not None:
+            fx = torch.as_tensor(np.asarray(fixed, dtype=np.uint8), device="cuda").contiguous()
+        s = self._sys_for(n, box, pbc, sysbuf)
+        b, p = _box_pbc(box, pbc)
+        trace = np.zeros(int(max_steps) + 1)
+        steps, fm, conv = ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32()
+        info = Info()
+        _check(lib().ctbop_relax_fire(self.ctx, int(n), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(v.data_ptr()),
+                                      ctypes.c_void_p(types.data_ptr()),
+                                      ctypes.c_void_p(fx.data_ptr()) if fx is not None else None,
+                                      b.ctypes.data, p.ctypes.data, float(Q), float(fmax), int(max_steps),
+                                      float(dt0), float(dtmax), s.ptr(), s.nbytes, ctypes.c_void_p(F.data_ptr()),
+                                      ctypes.c_void_p(q.data_ptr()), trace.ctypes.data, ctypes.byref(steps),
+                                      ctypes.byref(fm), ctypes.byref(conv), ctypes.byref(info), _stream()))
+        k = steps.value
+        return (x.reshape(3, n).t().contiguous(), F.reshape(3, n).t().contiguous(), q, trace[:k + 1], k, fm.value,
+                bool(conv.value), info.as_dict())
 
     def removal_energies(self, pos, types, box, pbc, candidates, Q=0.0, concurrency: int = 16):
         """dE_i = E(X without atom i) - E(X) for every candidate i, charges

@@ -800,6 +800,95 @@ int ctbop_md_run_nvt(ctbop_ctx *ctx, int n, double *x, double *v, const int32_t 
     return CTBOP_OK;
 }
 
+int ctbop_relax_fire(ctbop_ctx *ctx, int n, double *x, double *v, const int32_t *types, const uint8_t *fixed,
+                     const double *box, const int *pbc, double Q, double fmax, int max_steps, double dt0,
+                     double dtmax, void *sys, size_t sys_bytes, double *F, double *q, double *E_trace,
+                     int *steps_out, double *fmax_out, int *converged, ctbop_info *info, void *stream)
+{
+    if (!x || !v || !types || !F || !q || max_steps < 0) return fail(CTBOP_E_INVAL, "bad argument");
+    if (!(fmax > 0) || !(dt0 > 0) || !(dtmax >= dt0)) return fail(CTBOP_E_INVAL, "need fmax, dt0 > 0, dtmax >= dt0");
+    // the published FIRE constants
+    const int n_min = 5;
+    const double f_inc = 1.1, f_dec = 0.5, alpha_start = 0.1, f_alpha = 0.99;
+    Prep P;
+    int rc = prepare(ctx, n, box, pbc, sys, sys_bytes, stream, P);
+    if (rc) return rc;
+    Seg S = P.L.seg;
+    S.x = x;
+    S.type = types;
+    S.F = F;
+    S.q_out = q;
+    S.E_out = nullptr;
+    S.Q = Q;
+    hipLaunchKernelGGL(k_set_seg, dim3(1), dim3(1), 0, P.st, P.dseg, S);
+    HIPCHK(hipMemsetAsync(v, 0, 3 * sizeof(double) * (size_t)n, P.st));
+    const dim3 g(P.L.ntile), b(TILE), g1(1);
+    MdIO io;
+    io.x = x;
+    io.v = v;
+    io.F = F;
+    io.fixed = fixed;
+    io.dt = 0.0;
+    io.mass[0] = ctx->theta[25];
+    io.mass[1] = ctx->theta[26 + 25];
+    // the step's geometry changes by the minimiser's own rules, so the charge
+    // solve starts from the last charges without time extrapolation
+    const int flags = CTBOP_FLAG_WARM_START;
+    int iters = 0;
+    double red[6];
+    auto evaluate = [&]() -> int {
+        int r = eval_any(ctx, P, flags, &iters);
+        if (r) return r;
+        hipLaunchKernelGGL(k_fire_kick, g, b, 0, P.st, P.dtiles, P.dseg, io);
+        hipLaunchKernelGGL(k_fire_fin, g1, b, 0, P.st, P.dsegid, P.dseg, P.dke);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(red, P.dke, sizeof red, hipMemcpyDeviceToHost, P.st));
+        HIPCHK(hipStreamSynchronize(P.st));
+        const int code = (int)red[5];
+        if (code) return fail(map_status(code), status_text(code));
+        return CTBOP_OK;
+    };
+    rc = evaluate();
+    if (rc) return rc;
+    double dt = dt0, alpha = alpha_start;
+    int n_pos = 0, s = 0, conv = 0;
+    for (;;) {
+        if (E_trace) E_trace[s] = red[4];
+        const double fm = sqrt(red[3]);
+        if (fmax_out) *fmax_out = fm;
+        if (fm < fmax) {
+            conv = 1;
+            break;
+        }
+        if (s == max_steps) break;
+        double cv = 1.0, cf = 0.0;
+        if (s > 0) {
+            cv = 1.0 - alpha;
+            cf = red[2] > 0.0 ? alpha * sqrt(red[1]) / sqrt(red[2]) : 0.0;
+            if (red[0] > 0.0) {
+                if (++n_pos > n_min) {
+                    dt = std::min(dt * f_inc, dtmax);
+                    alpha *= f_alpha;
+                }
+            } else {
+                dt *= f_dec;
+                cv = cf = 0.0;
+                alpha = alpha_start;
+                n_pos = 0;
+            }
+        }
+        io.dt = dt;
+        hipLaunchKernelGGL(k_fire_kick_drift, g, b, 0, P.st, P.dtiles, P.dseg, io, cv, cf);
+        rc = evaluate();
+        if (rc) return rc;
+        s++;
+    }
+    if (steps_out) *steps_out = s;
+    if (converged) *converged = conv;
+    if (info) return fill_info(ctx, P, info);
+    return CTBOP_OK;
+}
+
 int ctbop_status(ctbop_ctx *ctx, void *sys, size_t sys_bytes, void *stream, int *code)
 {
     if (!ctx || !sys || !code) return fail(CTBOP_E_INVAL, "null argument");

@@ -1,5 +1,5 @@
 // k_md.h -- velocity-Verlet integration (user atom order), NVE or NVT with a
-// Nose-Hoover chain thermostat.
+// Nose-Hoover chain thermostat, and FIRE structure relaxation.
 //
 // Half kick + drift before the force evaluation, half kick after it.  Atoms
 // with a nonzero fixed flag neither move nor change velocity (the paper holds
@@ -164,6 +164,106 @@ __global__ void __launch_bounds__(TILE) k_count_fixed(const Tile *tiles, Seg *se
     const int i = T.row0 + threadIdx.x;
     double v[1] = {(i < S.n && fixed && fixed[i]) ? 1.0 : 0.0};
     tile_partials<1>(S, T.row0 / TILE, v, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Structure relaxation by FIRE (Bitzek et al., Phys. Rev. Lett. 97, 170201,
+// 2006): velocity-Verlet steps whose velocities are mixed towards the force
+// direction, v <- cv v + cf F, between steps (cv = 1 - alpha, cf = alpha
+// |v| / |F|; both 0 stop the system after an uphill step).  The host holds
+// the FIRE state (dt, alpha, the count of downhill steps) and reads the four
+// reductions of each step: P = F.v, |v|^2, |F|^2 and max_i |F_i|^2 over the
+// mobile atoms.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(TILE) k_fire_kick_drift(const Tile *tiles, Seg *segs, MdIO io, double cv,
+                                                          double cf)
+{
+    const Tile T = my_tile(tiles);
+    const Seg &S = segs[T.seg];
+    const int i = T.row0 + threadIdx.x;
+    if (i >= S.n) return;
+    if (io.fixed && io.fixed[i]) return;
+    const double a = 0.5 * io.dt * ACC_UNIT / io.mass[S.type[i]];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const double f = io.F[d * S.n + i];
+        double v = cv * io.v[d * S.n + i] + cf * f;
+        v += a * f;
+        io.v[d * S.n + i] = v;
+        io.x[d * S.n + i] += io.dt * v;
+    }
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// max over the block (result valid in thread 0)
+__device__ __forceinline__ double block_max(double v, double *lds /* 4 */)
+{
+    const double m = wave_max(v);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = m;
+    __syncthreads();
+    const double r = fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
+    __syncthreads();
+    return r;
+}
+
+// second half kick (skipped with dt = 0) and the tile's FIRE reductions:
+// partials 0..2 = P, |v|^2, |F|^2 (sums), 3 = max |F_i|^2
+__global__ void __launch_bounds__(TILE) k_fire_kick(const Tile *tiles, Seg *segs, MdIO io)
+{
+    const Tile T = my_tile(tiles);
+    const Seg &S = segs[T.seg];
+    __shared__ double lds[12];
+    __shared__ double ldm[4];
+    const int i = T.row0 + threadIdx.x;
+    double r[3] = {0.0, 0.0, 0.0}, f2 = 0.0;
+    if (i < S.n && !(io.fixed && io.fixed[i])) {
+        const double a = 0.5 * io.dt * ACC_UNIT / io.mass[S.type[i]];
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const double f = io.F[d * S.n + i];
+            double v = io.v[d * S.n + i];
+            if (io.dt != 0.0) {
+                v += a * f;
+                io.v[d * S.n + i] = v;
+            }
+            r[0] += f * v;
+            r[1] += v * v;
+            f2 += f * f;
+        }
+        r[2] = f2;
+    }
+    tile_partials<3>(S, T.row0 / TILE, r, lds);
+    const double m = block_max(f2, ldm);
+    if (threadIdx.x == 0) S.part[(size_t)(T.row0 / TILE) * NPART + 3] = m;
+}
+
+// out[0..3] = P, |v|^2, |F|^2, max |F_i|^2; out[4] = potential energy;
+// out[5] = the segment's status word
+__global__ void k_fire_fin(const int *seg_ids, Seg *segs, double *out)
+{
+    const Seg &S = segs[seg_ids[blockIdx.x]];
+    __shared__ double lds[12];
+    __shared__ double ldm[4];
+    double tot[3];
+    seg_total<3>(S, lds, tot);
+    double m = 0.0;
+    for (int t = threadIdx.x; t < S.ntile; t += TILE) m = fmax(m, S.part[(size_t)t * NPART + 3]);
+    m = block_max(m, ldm);
+    if (threadIdx.x == 0) {
+        out[0] = tot[0];
+        out[1] = tot[1];
+        out[2] = tot[2];
+        out[3] = m;
+        out[4] = S.sst->energy;
+        out[5] = (double)S.sst->status;
+    }
 }
 
 } // namespace ctbop
