@@ -324,6 +324,35 @@ def removal_bench(ct, theta, concurrency: int = 32):
             "below_6.5eV": int((dE < 6.5).sum())}
 
 
+def rings_bench(ct, theta):
+    """Ring statistics of two large carbon networks: a 1M-atom graphene sheet
+    with 400 Stone-Wales defects and thermal noise (sp2, the paper's graphene
+    layer) and a 250k-atom random carbon network at 2.0 g/cm^3 (the
+    disordered film before annealing: rings of 3-8 members, chains)."""
+    import torch
+    from ctbop_inputs import generators as G
+    out = {}
+    for name, s, kw in (("graphene_sw_1m", G.graphene(500, 500, 400, seed=1007, sigma=0.05), dict(r_bond=1.7)),
+                        ("random_carbon_250k", G.random_system(250000, 1.0, 2.0, True, seed=1008, dmin=1.4),
+                         dict(r_bond=1.95))):
+        pot = ct.Potential(theta)
+        pot.rings(s.pos, s.types, s.box, s.pbc, **kw)                    # lists built, warm-up
+        pot.profile(enable=True, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = pot.rings(s.pos, s.types, s.box, s.pbc, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = pot.profile(enable=False, reset=True)
+        out[name] = {"atoms": int(s.n), "seconds": dt, "atoms_per_s": s.n / dt,
+                     "rings_by_size": {str(k): int(r["counts"][k]) for k in range(3, 9)},
+                     "bonds": r["bonds"], "chain_bonds": r["chain_bonds"],
+                     "kernel_us": {k: prof[k][0] * 1e3 for k in ("ring_adj", "rings", "ring_chain")}}
+        del pot
+        torch.cuda.empty_cache()
+    return out
+
+
 def measure_copy_peak(torch, mib: int = 2048, reps: int = 10):
     """Device-to-device copy bandwidth on this GPU (read + write bytes per
     second, best of `reps` copies of `mib` MiB), the practical HBM ceiling
@@ -385,6 +414,7 @@ def main():
     ap.add_argument("--nvt-steps", type=int, default=50)
     ap.add_argument("--no-relax", action="store_true", help="skip the FIRE relaxation measurement")
     ap.add_argument("--relax-steps", type=int, default=100)
+    ap.add_argument("--no-rings", action="store_true", help="skip the ring-statistics measurement")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (scales HBM byte counters)")
     args = ap.parse_args()
@@ -571,6 +601,10 @@ def main():
         print("bench: removal energies (desorption test)", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         out["removal"] = removal_bench(ct, theta)
+    if not args.no_rings:
+        print("bench: ring statistics", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        out["rings"] = rings_bench(ct, theta)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(theta, args.cpu_nx, args.cpu_steps)

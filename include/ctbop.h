@@ -246,6 +246,49 @@ int ctbop_relax_fire(ctbop_ctx *ctx, int n, double *x_dev, double *v_dev, const 
                      double *F_dev, double *q_dev, double *E_trace_host, int *steps_out, double *fmax_out,
                      int *converged, ctbop_info *info, void *stream);
 
+/* Ring statistics of the carbon bond graph: the paper draws its growth and
+ * anneal structures as C rings by size (3-8 members), C chains, and the
+ * in-plane orientation of every 6-membered ring, a hue that repeats every 60
+ * degrees and is zero when two opposite vertices point along the substrate's
+ * [11-20] direction (growth-simulation and annealing sections).  Neither bonds
+ * nor rings are defined there; here a bond joins two C atoms (type 1) with an
+ * image of one within r_bond of the other, and a ring is a shortest-path
+ * ring (Franzblau, Phys. Rev. B 44, 4925, 1991): a simple cycle of at most
+ * max_size (3..8) bonds such that for every two of its atoms the shorter way
+ * round is a shortest path of the whole bond graph.  A chain bond is a bond
+ * on no such ring.  The orientation of a 6-ring: each of its three
+ * vertex-to-opposite-vertex vectors, projected on the plane with normal
+ * normal_host, makes an angle theta_k with ref_host (projected on that
+ * plane); the orientation is arg(sum_k exp(6 i theta_k)) / 6 in [0, 60)
+ * degrees, and the ring enters the histogram (nbins bins over [0, 60)) if its
+ * own normal is within max_tilt_deg of normal_host (all rings at >= 90).
+ *   x_dev, types_dev   positions (SoA) and types on the device; the lists of
+ *                      sys_dev are brought up to date for them (as an
+ *                      evaluation would), nothing else in it changes
+ *   r_bond             in (0, S_CC]: the covalent list holds pairs up to S_CC
+ *   ws_dev             device workspace of ctbop_rings_bytes() bytes
+ *   counts_host[9]     rings by size (index = size; 0..2 stay 0)
+ *   bonds_host[2]      C-C bonds, chain bonds
+ *   hist_host          NULL or nbins counts
+ *   ring_list_dev      NULL or ring_cap * 9 int32 on the device: size, then the
+ *                      user indices in ring order from the smallest, towards
+ *                      its smaller neighbour, -1 padded; ring_orient_dev
+ *                      (NULL or ring_cap doubles) the orientation (-1: not a
+ *                      6-ring).  The order of the rings in the list is not
+ *                      fixed.  n_rings_host gets the number of rings found,
+ *                      which may exceed ring_cap (then only ring_cap are listed).
+ * E_INVAL for max_size outside 3..8, r_bond outside (0, S_CC], a periodic
+ * width below max_size * r_bond (a ring could wind around the cell), a zero
+ * normal or a reference along it; E_NEIGH_OVERFLOW when a C atom has more
+ * than 12 C neighbours.  Waits for the stream. */
+int ctbop_rings_bytes(ctbop_ctx *ctx, int n, const double *box_host, const int *pbc_host, int nbins, size_t *bytes);
+int ctbop_rings(ctbop_ctx *ctx, int n, const double *x_dev, const int32_t *types_dev, const double *box_host,
+                const int *pbc_host, void *sys_dev, size_t sys_bytes, double r_bond, int max_size,
+                const double *normal_host, const double *ref_host, double max_tilt_deg, int nbins, void *ws_dev,
+                size_t ws_bytes, int64_t *counts_host, int64_t *bonds_host, int64_t *hist_host,
+                int32_t *ring_list_dev, double *ring_orient_dev, int64_t ring_cap, int64_t *n_rings_host,
+                void *stream);
+
 /* Device status word of `sys` (waits for the stream). */
 int ctbop_status(ctbop_ctx *ctx, void *sys_dev, size_t sys_bytes, void *stream, int *code);
 
@@ -257,7 +300,8 @@ int ctbop_status(ctbop_ctx *ctx, void *sys_dev, size_t sys_bytes, void *stream, 
  * Classes: 0 charge-solve matrix-vector product, 1 Coulomb force/energy
  * gather, 2 Coulomb matrix assembly, 3 covalent bond pass, 4 covalent force
  * gather, 5 charge-solve update, 6 charge-solve direction, 7 list build,
- * 8 sliced copy of the Coulomb rows. */
+ * 8 sliced copy of the Coulomb rows, 9 carbon adjacency, 10 ring search,
+ * 11 chain bonds. */
 int ctbop_profile(ctbop_ctx *ctx, int enable, int reset, void *stream, double *ms_out, long *count_out, int nk);
 
 /* Message of the last error on the calling thread ("" if none). */

@@ -55,7 +55,8 @@ _lib = None
 EXPORTS = ("ctbop_default_opts", "ctbop_create", "ctbop_destroy", "ctbop_system_bytes",
            "ctbop_compute_energy_forces_charges", "ctbop_md_run", "ctbop_status", "ctbop_last_error",
            "ctbop_debug_lists", "ctbop_profile", "ctbop_set_params", "ctbop_param_grad_bytes", "ctbop_param_grad",
-           "ctbop_removal_bytes", "ctbop_removal_energies", "ctbop_md_run_nvt", "ctbop_relax_fire")
+           "ctbop_removal_bytes", "ctbop_removal_energies", "ctbop_md_run_nvt", "ctbop_relax_fire",
+           "ctbop_rings_bytes", "ctbop_rings")
 
 
 def lib():
@@ -87,6 +88,9 @@ def lib():
         L.ctbop_relax_fire.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, dbl, dbl, i32, dbl, dbl, vp, sz, vp, vp, vp,
                                        ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.POINTER(i32),
                                        ctypes.POINTER(Info), vp]
+        L.ctbop_rings_bytes.argtypes = [vp, i32, vp, vp, i32, ctypes.POINTER(sz)]
+        L.ctbop_rings.argtypes = [vp, i32, vp, vp, vp, vp, vp, sz, dbl, i32, vp, vp, dbl, i32, vp, sz, vp, vp, vp, vp,
+                                  vp, ctypes.c_int64, vp, vp]
         L.ctbop_removal_energies.argtypes = [vp, i32, vp, vp, vp, vp, dbl, vp, i32, vp, sz, vp, vp, vp, vp]
         _lib = L
     return _lib
@@ -334,6 +338,46 @@ class Potential:
         return (x.reshape(3, n).t().contiguous(), F.reshape(3, n).t().contiguous(), q, trace[:k + 1], k, fm.value,
                 bool(conv.value), info.as_dict())
 
+    def rings(self, pos, types, box, pbc, r_bond=1.95, max_size=8, normal=(0.0, 0.0, 1.0), ref=(1.0, 0.0, 0.0),
+              max_tilt=90.0, nbins=60, list_cap=0, sysbuf=None):
+        """Shortest-path rings of the C bond graph, chain bonds and the 6-ring
+        orientation histogram.  pos (n,3).  Returns dict(counts (9,) by ring
+        size, bonds, chain_bonds, hist (nbins,), n_rings, and with list_cap > 0
+        rings: list of vertex tuples (canonical order) and orient: numpy per
+        listed ring (-1 for non-6-rings), in the device's order)."""
+        torch = _torch()
+        pos = torch.as_tensor(pos, dtype=torch.float64, device="cuda").reshape(-1, 3)
+        types = torch.as_tensor(types, dtype=torch.int32, device="cuda").contiguous()
+        n = types.shape[0]
+        x = pos.t().contiguous().reshape(-1)
+        s = self._sys_for(n, box, pbc, sysbuf)
+        b, p = _box_pbc(box, pbc)
+        nb = ctypes.c_size_t()
+        _check(lib().ctbop_rings_bytes(self.ctx, int(n), b.ctypes.data, p.ctypes.data, int(nbins), ctypes.byref(nb)))
+        ws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+        cap = int(list_cap)
+        lst = torch.empty((max(cap, 1), 9), dtype=torch.int32, device="cuda")
+        ori = torch.empty(max(cap, 1), dtype=torch.float64, device="cuda")
+        nv = np.ascontiguousarray(normal, dtype=np.float64)
+        rv = np.ascontiguousarray(ref, dtype=np.float64)
+        counts = np.zeros(9, dtype=np.int64)
+        bonds = np.zeros(2, dtype=np.int64)
+        hist = np.zeros(int(nbins), dtype=np.int64)
+        nr = ctypes.c_int64()
+        _check(lib().ctbop_rings(self.ctx, int(n), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(types.data_ptr()),
+                                 b.ctypes.data, p.ctypes.data, s.ptr(), s.nbytes, float(r_bond), int(max_size),
+                                 nv.ctypes.data, rv.ctypes.data, float(max_tilt), int(nbins),
+                                 ctypes.c_void_p(ws.data_ptr()), int(nb.value), counts.ctypes.data, bonds.ctypes.data,
+                                 hist.ctypes.data, ctypes.c_void_p(lst.data_ptr()) if cap else None,
+                                 ctypes.c_void_p(ori.data_ptr()) if cap else None, cap, ctypes.byref(nr), _stream()))
+        out = dict(counts=counts, bonds=int(bonds[0]), chain_bonds=int(bonds[1]), hist=hist, n_rings=int(nr.value))
+        if cap:
+            k = min(cap, int(nr.value))
+            L = lst[:k].cpu().numpy()
+            out["rings"] = [tuple(int(v) for v in row[1:1 + row[0]]) for row in L]
+            out["orient"] = ori[:k].cpu().numpy()
+        return out
+
     def removal_energies(self, pos, types, box, pbc, candidates, Q=0.0, concurrency: int = 16):
         """dE_i = E(X without atom i) - E(X) for every candidate i, charges
         re-equilibrated in both (the desorption test).  pos (n,3), types (n,)
@@ -359,7 +403,8 @@ class Potential:
                                             dE.ctypes.data, it.ctypes.data, _stream()))
         return float(E[0]), dE[:m], it[:m]
 
-    KERNELS = ("spmv", "force_coul", "assemble", "bond", "force_cov", "cg_update", "cg_dir", "build", "hslice")
+    KERNELS = ("spmv", "force_coul", "assemble", "bond", "force_cov", "cg_update", "cg_dir", "build", "hslice",
+               "ring_adj", "rings", "ring_chain")
 
     def profile(self, enable=True, reset=True):
         """Per-kernel event timing: returns {name: (ms_total, launches)} accumulated

@@ -409,8 +409,10 @@ int prepare(ctbop_ctx *ctx, int n, const double *box, const int *pbc, void *sys,
     return CTBOP_OK;
 }
 
+// Sorted frame and neighbour lists for the current positions (the lists are
+// rebuilt when an atom has moved more than half the skin, or on request).
 template <typename R>
-int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *iters_out)
+void launch_lists(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags)
 {
     const int nt = P.L.ntile;
     const dim3 g(nt), b(TILE), g1(1);
@@ -435,6 +437,18 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
     }
     hipLaunchKernelGGL(k_rev, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_mark_built, g1, dim3(64), 0, st, sid, P.dseg, 1);
+}
+
+// One evaluation: sorted frame and lists, bond pass, Coulomb rows, charge
+// solve, forces and energy.
+template <typename R>
+int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *iters_out)
+{
+    const int nt = P.L.ntile;
+    const dim3 g(nt), b(TILE), g1(1);
+    hipStream_t st = P.st;
+    const int *sid = P.dsegid;
+    launch_lists<R>(ctx, P, prm, flags);
     {
         Timed t(ctx, 3, st);
         hipLaunchKernelGGL((k_bond<R>), g, b, 0, st, P.dtiles, P.dseg, ctx->pd);
@@ -493,6 +507,12 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
     hipLaunchKernelGGL(k_fin_energy, g1, b, 0, st, sid, P.dseg, 0);
     HIPCHK(hipGetLastError());
     return CTBOP_OK;
+}
+
+void lists_any(ctbop_ctx *ctx, Prep &P, int flags)
+{
+    if (ctx->opts.fp64) launch_lists<double>(ctx, P, ctx->pd, flags);
+    else launch_lists<float>(ctx, P, ctx->pf, flags);
 }
 
 int eval_any(ctbop_ctx *ctx, Prep &P, int flags, int *iters)
@@ -979,3 +999,4 @@ int ctbop_debug_lists(ctbop_ctx *ctx, int n, void *sys, size_t sys_bytes, int lo
 #include "server.h"
 #include "removal.h"
 #include "adjoint_host.h"
+#include "rings_host.h"
