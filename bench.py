@@ -535,6 +535,7 @@ def main():
             "workload": f"4H-SiC(0001) Si-face stepped slab {args.nx}x{args.nx} cells x {args.nbil} bilayers, "
                         f"30% top-Si depleted, {n} atoms, 2500 K NVE, dt 0.5 fs, charges to 1e-9 every step",
             "n_atoms": n, "cg_iters_last_step": info["cg_iters"], "nnz_coulomb": nnz, "nnz_coulomb_wide": nnz_wide,
+            "nnz_coulomb_slots": int(info["nnz_coul_slots"]),
             "nnz_long_list": int(info["nnz_long"]),
             "nnz_short": int(info["nnz_short"]),
             "cg_iters_per_step": iters / args.steps, "list_rebuilds": int(info["n_rebuild"]) - int(info_w["n_rebuild"]),

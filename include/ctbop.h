@@ -122,6 +122,8 @@ typedef struct {
     unsigned long long nnz_coul;  /* Coulomb entries inside rc at the last assembly */
     unsigned long long nnz_coul_wide; /* of which stored with full (32-bit) indices in the
                                          solver's sliced copy (the rest: 16-bit offsets) */
+    unsigned long long nnz_coul_slots; /* entry slots the solver's product reads: per
+                                          slice of 64 rows, 64 x its longest row */
 } ctbop_info;
 
 /* Fill *o with the defaults above. */

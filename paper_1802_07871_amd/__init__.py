@@ -45,7 +45,8 @@ class Info(ctypes.Structure):
                 ("max_long", ctypes.c_int), ("max_short", ctypes.c_int),
                 ("nnz_long", ctypes.c_ulonglong), ("nnz_short", ctypes.c_ulonglong), ("n_rebuild", ctypes.c_int),
                 ("cg_iters_total", ctypes.c_ulonglong), ("cg_res0", ctypes.c_double),
-                ("nnz_coul", ctypes.c_ulonglong), ("nnz_coul_wide", ctypes.c_ulonglong)]
+                ("nnz_coul", ctypes.c_ulonglong), ("nnz_coul_wide", ctypes.c_ulonglong),
+                ("nnz_coul_slots", ctypes.c_ulonglong)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

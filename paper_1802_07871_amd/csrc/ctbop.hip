@@ -217,6 +217,7 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
     size_t o_lcnt = take(4 * np), o_lidx = take(4 * np * S.Wl), o_H = take(rsz * np * S.Wl);
     size_t o_hcnt = take(4 * np), o_hidx = take(4 * np * S.Wl), o_Hr = take(rsz * np * S.Wl);
     size_t o_hsidx = take(4 * np * S.Wl), o_hs16 = take(2 * np * S.Wl), o_hwide = take(np), o_swide = take(np / SLICE);
+    size_t o_hperm = take(np);
     size_t o_scnt = take(4 * np), o_sidx = take(4 * np * S.Ws), o_srev = take(np * S.Ws);
     size_t o_bcnt = take(4 * np), o_bidx = take(4 * np * S.Wb), o_bsrev = take(np * S.Wb), o_cmap = take(np * S.Ws),
            o_slot = take(v4 * np * S.Wb);
@@ -248,6 +249,7 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
         S.hs16 = (uint16_t *)(base + o_hs16);
         S.hwide = (uint8_t *)(base + o_hwide);
         S.swide = (uint8_t *)(base + o_swide);
+        S.hperm = (uint8_t *)(base + o_hperm);
         S.scnt = (int *)(base + o_scnt);
         S.sidx = (uint32_t *)(base + o_sidx);
         S.srev = (uint8_t *)(base + o_srev);
@@ -557,6 +559,7 @@ int fill_info(ctbop_ctx *ctx, Prep &P, ctbop_info *info)
     info->cg_res0 = ss.res0;
     info->nnz_coul = (unsigned long long)ss.nnz_coul;
     info->nnz_coul_wide = (unsigned long long)ss.nnz_wide;
+    info->nnz_coul_slots = (unsigned long long)ss.nnz_slots;
     if (ss.status) return fail(info->status, status_text(ss.status));
     return CTBOP_OK;
 }
@@ -975,11 +978,12 @@ int ctbop_debug_lists(ctbop_ctx *ctx, int n, void *sys, size_t sys_bytes, int lo
         if (ctx->opts.fp64) return ((const double *)xs.data())[4 * s + a];
         return (double)((const float *)xs.data())[4 * s + a];
     };
-    auto emit = [&](int s, const uint32_t *row, int cnt, int cap, int *counts, int *jj, double *dd) {
+    auto emit = [&](int s, const uint32_t *row, size_t stride, int cnt, int cap, int *counts, int *jj, double *dd) {
         const int i = perm[s];
         counts[i] = std::min(cnt, cap);
         for (int e = 0; e < counts[i]; e++) {
-            const int j = (int)(row[e] & J_MASK), c = (int)(row[e] >> CODE_SHIFT);
+            const uint32_t ent = row[(size_t)e * stride];
+            const int j = (int)(ent & J_MASK), c = (int)(ent >> CODE_SHIFT);
             const int d0 = c / 49 - 3, d1 = (c / 7) % 7 - 3, d2 = c % 7 - 3;
             jj[(size_t)i * cap + e] = perm[j];
             for (int a = 0; a < 3; a++)
@@ -988,8 +992,8 @@ int ctbop_debug_lists(ctbop_ctx *ctx, int n, void *sys, size_t sys_bytes, int lo
         }
     };
     for (int s = 0; s < n; s++) {
-        if (cl) emit(s, &lidx[(size_t)s * S.Wl], lcnt[s], long_cap, cl, jl, dl);
-        if (cs) emit(s, &sidx[(size_t)s * S.Ws], scnt[s], short_cap, cs, js, ds);
+        if (cl) emit(s, &lidx[(size_t)s * S.Wl], 1, lcnt[s], long_cap, cl, jl, dl);
+        if (cs) emit(s, &sidx[(size_t)s * S.Ws], 1, scnt[s], short_cap, cs, js, ds);
     }
     return CTBOP_OK;
 }

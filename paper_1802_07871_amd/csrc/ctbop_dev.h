@@ -76,6 +76,7 @@ struct SegState {
     double res0;                              // starting residual of the last solve
     double nnz_coul;                          // Coulomb entries inside rc at the last assembly
     double nnz_wide;                          // of which in slices that keep full entries
+    double nnz_slots;                         // entry slots the sliced product reads: 64 x longest row, per slice
 };
 
 // ---------------------------------------------------------------------------
@@ -126,21 +127,29 @@ struct Seg {
     // In the sliced copy the neighbour row is stored as a 16-bit offset from
     // the slice's first row (hs16, offset + 32768) when every entry of the
     // slice lies within that window (swide = 0), else as the full entry
-    // (hsidx); hwide flags the rows that need the full form.
+    // (hsidx); hwide flags the rows that need the full form wherever in its
+    // tile the row is placed.  Within each tile the rows take the slice
+    // slots in order of decreasing length (ties by row), so that the rows of
+    // a slice have similar lengths and a wave reads few padding slots; slot t
+    // of a tile holds row hperm[t] of that tile.
     uint32_t *hsidx;   // [npad * Wl]
     uint16_t *hs16;    // [npad * Wl]
     uint8_t *hwide;    // [npad]
-    uint8_t *swide;    // [npad / SLICE]
+    uint8_t *swide;    // [npad / SLICE], per slice of slots
+    uint8_t *hperm;    // [npad]
     void *H;           // [npad * Wl] float / double
     // covalent list: r < S_ij + skin at the last build, row-major, stride Ws
     int *scnt;         // [npad]
     uint32_t *sidx;    // [npad * Ws]
     uint8_t *srev;     // [npad * Ws]: slot of the reverse entry in the partner's row
     // Bonds of the current step: the covalent-list entries inside S_ij (FP64
-    // distance), compacted in list order into rows of stride Wb; cmap maps
+    // distance), compacted in list order into rows of width Wb; cmap maps
     // each list slot to its bond index (255: outside) and bsrev holds each
     // bond's reverse list slot, so the reverse bond of (m, e) in the partner
-    // i's row is cmap[i][bsrev[m][e]].
+    // i's row is cmap[i][bsrev[m][e]].  These arrays are sliced like the
+    // solver's copy (entry e of row s at sliced(s, e, W)): a wave reading
+    // entry e of its 64 rows reads one contiguous segment, and rows of nearby
+    // atoms share cache lines.
     int *bcnt;         // [npad]
     uint32_t *bidx;    // [npad * Wb]
     uint8_t *bsrev;    // [npad * Wb]
@@ -195,6 +204,16 @@ __device__ __forceinline__ size_t slice_base(int s, int W)
 {
     return (size_t)(s & ~(SLICE - 1)) * (size_t)W + (size_t)(s & (SLICE - 1));
 }
+
+// Entry e of row s in a sliced array of row width W
+__device__ __forceinline__ size_t sliced(int s, int e, int W) { return slice_base(s, W) + (size_t)e * SLICE; }
+
+// A row of a sliced array, indexed by entry
+template <typename T> struct SRow {
+    T *p;
+    __device__ __forceinline__ T &operator[](int e) const { return p[(size_t)e * SLICE]; }
+};
+template <typename T> __device__ __forceinline__ SRow<T> srow(T *a, int s, int W) { return SRow<T>{a + slice_base(s, W)}; }
 
 __device__ __forceinline__ int code_of(int d0, int d1, int d2) { return ((d0 + 3) * 7 + (d1 + 3)) * 7 + (d2 + 3); }
 

@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(TILE) k_bond_dual(const Tile *tiles, Seg *segs
     double ew = 0.0;
     if (s < S.n) {
         const double4 *xs = S.xs64;
-        const uint32_t *row = S.bidx + (size_t)s * S.Wb;
+        const SRow<const uint32_t> row = srow<const uint32_t>(S.bidx, s, S.Wb);
         double *slot = A.slotd + blockIdx.y * A.slot_stride + (size_t)s * S.Wb * 6;
         const double4 li = xs[s];
         const int ti = (int)li.w;
@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov_dual(const Tile *tiles, Seg 
         const double4 lm = xs[m];
         const int tm = (int)lm.w;
         const int ns = S.bcnt[m];
-        const uint32_t *row = S.bidx + (size_t)m * S.Wb;
+        const SRow<const uint32_t> row = srow<const uint32_t>(S.bidx, m, S.Wb);
         Dual fx(0.0), fy(0.0), fz(0.0);
         for (int e = 0; e < ns; e++) {
             const uint32_t ent = row[e];
@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov_dual(const Tile *tiles, Seg 
             const Dual dv = pair_dvdr<Dual>(P, pp, Dual(r), b) * ir;
             Dual ax = -dv * d.x, ay = -dv * d.y, az = -dv * d.z;
             const int ni = S.bcnt[i];
-            const uint32_t *rowi = S.bidx + (size_t)i * S.Wb;
+            const SRow<const uint32_t> rowi = srow<const uint32_t>(S.bidx, i, S.Wb);
             const R3<Dual> dd = {Dual(d.x), Dual(d.y), Dual(d.z)};
             for (int t = 0; t < ni; t++) {
                 if (t == srev) continue;

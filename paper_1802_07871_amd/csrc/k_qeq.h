@@ -81,7 +81,7 @@ __device__ __forceinline__ double entry_r(const typename Vec4<R>::type &li, cons
 }
 
 // Assemble the Coulomb rows of the step: the list entries inside rc, in list
-// order, into hidx/Hr (group ballots give each lane its slot), and the
+// order, into hidx/Hr (group ballots give each lane its place), and the
 // starting residual r = -(H q0 + chi) + mu_prev.
 template <typename R, int LPR>
 __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs, Params<double> PD)
@@ -97,6 +97,14 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
     constexpr int G = TILE / LPR;
     const int lane = threadIdx.x % LPR;
     const unsigned below = (1u << lane) - 1u;
+    // Each group stages its kept entries in LDS and writes them out FL at a
+    // time: whole 128-byte lines of hidx (rows start on 2 KB boundaries), so
+    // no line of the output is written in pieces.
+    constexpr int FL = 32;
+    __shared__ uint32_t bidx_lds[G][FL + LPR];
+    __shared__ R bval_lds[G][FL + LPR];
+    uint32_t *bi = bidx_lds[threadIdx.x / LPR];
+    R *bv = bval_lds[threadIdx.x / LPR];
     for (int k = threadIdx.x / LPR; k < TILE; k += G) {
         const int s = T.row0 + k;
         if (s >= S.n) {
@@ -113,9 +121,9 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
         uint32_t *hrow = S.hidx + (size_t)s * S.Wl;
         R *vrow = Hr + (size_t)s * S.Wl;
         double acc = 0.0;
-        int pos = 0;
+        int nbuf = 0, done = 0;
         bool wide = false;
-        const int sbase = s & ~(SLICE - 1);
+        const int tbase = s & ~(TILE - 1);      // the row may take any slice of its tile
         for (int e0 = 0; e0 < cnt; e0 += LPR) {
             const int e = e0 + lane;
             bool in = false;
@@ -133,21 +141,48 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
             }
             const unsigned gm = group_ballot<LPR>(in);
             if (in) {
-                const int at = pos + __popc(gm & below);
+                const int at = nbuf + __popc(gm & below);
                 const R c = (R)coul64_val(PD, ti * 2 + tj, r);
-                hrow[at] = ent;
-                vrow[at] = c;
+                bi[at] = ent;
+                bv[at] = c;
                 acc += (double)c * S.q[j];
-                const int off = j - sbase;
-                wide = wide || off < -32768 || off > 32767;
+                const int off = j - tbase;
+                wide = wide || off - (TILE - SLICE) < -32768 || off > 32767;
             }
-            pos += __popc(gm);
+            nbuf += __popc(gm);
+            __builtin_amdgcn_wave_barrier();
+            if (nbuf >= FL) {
+                for (int t = lane; t < FL; t += LPR) {
+                    hrow[done + t] = bi[t];
+                    vrow[done + t] = bv[t];
+                }
+                const int rest = nbuf - FL;      // < LPR
+                uint32_t ri = 0;
+                R rv = (R)0;
+                if (lane < rest) {
+                    ri = bi[FL + lane];
+                    rv = bv[FL + lane];
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (lane < rest) {
+                    bi[lane] = ri;
+                    bv[lane] = rv;
+                }
+                __builtin_amdgcn_wave_barrier();
+                done += FL;
+                nbuf = rest;
+            }
         }
+        for (int t = lane; t < nbuf; t += LPR) {
+            hrow[done + t] = bi[t];
+            vrow[done + t] = bv[t];
+        }
+        __builtin_amdgcn_wave_barrier();
         acc = group_sum<LPR>(acc);
         wide = group_ballot<LPR>(wide) != 0u;
         if (lane == 0) {
             const double qs = S.q[s];
-            S.hcnt[s] = pos;
+            S.hcnt[s] = done + nbuf;
             S.hwide[s] = wide ? 1 : 0;
             S.jd[s] = PD.J[ti];
             S.r[s] = -(PD.J[ti] * qs + acc + PD.chi[ti]) + mprev;
@@ -157,11 +192,12 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
 }
 
 // Sliced copy (hsidx, H) of the step's rows (hidx, Hr) for the charge-solve
-// product, and the block-Jacobi preconditioner.  Each block transposes its
-// tile through LDS in chunks of HS_CH entries: HS_CH lanes read a row
-// segment, then each lane writes its row's chunk as slice columns (both sides
-// touch contiguous memory) and adds the entries whose neighbour lies in its
-// own BK-row block to that block row, in list order.  The tile's blocks (J on
+// product, and the block-Jacobi preconditioner.  Each block first orders its
+// tile's rows by decreasing length (the slot order, hperm), then transposes
+// the tile through LDS in chunks of HS_CH entries: HS_CH lanes read a row
+// segment, then each lane writes the chunk of its slot's row as slice columns
+// (both sides touch contiguous memory) and adds the entries whose neighbour
+// lies in the row's own BK-row block to that block row, in list order.  The tile's blocks (J on
 // the diagonal) are then inverted in LDS by Gauss-Jordan elimination (H is
 // SPD, so no pivoting), symmetrised and written with their row sums; the
 // tile's partial sums of r m1 and m1 start the projection.
@@ -180,30 +216,53 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
     __shared__ double lds[4 * 5];
     uint32_t(*ci)[HS_CH + 1] = reinterpret_cast<uint32_t(*)[HS_CH + 1]>(buf);
     R(*cv)[HS_CH + 1] = reinterpret_cast<R(*)[HS_CH + 1]>(buf + CI_BYTES);
-    const int own = T.row0 + threadIdx.x;
+    __shared__ int slot_row[TILE];
+    __shared__ uint8_t wide_row[TILE];
+    __shared__ uint8_t sw[TILE / SLICE];
+    const int tid = threadIdx.x;
+    const int own = T.row0 + tid;
     const bool live = own < S.n;
     const int own_cnt = live ? S.hcnt[own] : 0;
-    cnt_lds[threadIdx.x] = own_cnt;
+    cnt_lds[tid] = own_cnt;
+    wide_row[tid] = (live && S.hwide[own] != 0) ? 1 : 0;
+    __syncthreads();
+    // slot of each row: longer rows first, ties by row
+    int rank = 0;
+    for (int k = 0; k < TILE; k++) {
+        const int c = cnt_lds[k];
+        rank += (c > own_cnt || (c == own_cnt && k < tid)) ? 1 : 0;
+    }
+    slot_row[rank] = tid;
+    __syncthreads();
+    // from here to the block assembly, thread tid works on slot tid (row rk);
     // a wave is a slice: the 16-bit form unless one of its rows needs the full one
-    const bool swide = __ballot(live && S.hwide[own] != 0) != 0ull;
-    if ((threadIdx.x & (SLICE - 1)) == 0) S.swide[own / SLICE] = swide ? 1 : 0;
+    const int rk = slot_row[tid];
+    const int rrow = T.row0 + rk;
+    const int rcnt = cnt_lds[rk];
+    S.hperm[own] = (uint8_t)rk;
+    const bool swide = __ballot(wide_row[rk] != 0) != 0ull;
+    if ((tid & (SLICE - 1)) == 0) {
+        S.swide[own / SLICE] = swide ? 1 : 0;
+        sw[tid / SLICE] = swide ? 1 : 0;
+    }
     const int sbase = own & ~(SLICE - 1);
-    int m = own_cnt;
+    int m = rcnt;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0) mx[threadIdx.x >> 6] = m;
+    if ((tid & 63) == 0) mx[tid >> 6] = m;
+    const double slots = (tid & (SLICE - 1)) == 0 ? (double)(SLICE * m) : 0.0;
     __syncthreads();
     const int maxc = max(max(mx[0], mx[1]), max(mx[2], mx[3]));
     const R *Hr = reinterpret_cast<const R *>(S.Hr);
     R *H = reinterpret_cast<R *>(S.H);
-    const int lane = threadIdx.x % HS_CH;
+    const int lane = tid % HS_CH;
     const size_t b0 = slice_base(own, S.Wl);
-    const int bbase = own & ~(BK - 1);
+    const int bbase = rrow & ~(BK - 1);
     double hb[BK];
 #pragma unroll
     for (int t = 0; t < BK; t++) hb[t] = 0.0;
     for (int E0 = 0; E0 < maxc; E0 += HS_CH) {
-        for (int k = threadIdx.x / HS_CH; k < TILE; k += TILE / HS_CH) {
+        for (int k = tid / HS_CH; k < TILE; k += TILE / HS_CH) {
             const int e = E0 + lane;
             if (e < cnt_lds[k]) {
                 const size_t at = (size_t)(T.row0 + k) * S.Wl + e;
@@ -212,10 +271,10 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
             }
         }
         __syncthreads();
-        const int lim = min(HS_CH, own_cnt - E0);
+        const int lim = min(HS_CH, rcnt - E0);
         for (int e = 0; e < lim; e++) {
-            const uint32_t ent = ci[threadIdx.x][e];
-            const R v = cv[threadIdx.x][e];
+            const uint32_t ent = ci[rk][e];
+            const R v = cv[rk][e];
             if (swide) S.hsidx[b0 + (size_t)(E0 + e) * SLICE] = ent;
             else S.hs16[b0 + (size_t)(E0 + e) * SLICE] = (uint16_t)((int)(ent & J_MASK) - sbase + 32768);
             H[b0 + (size_t)(E0 + e) * SLICE] = v;
@@ -227,13 +286,18 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
         }
         __syncthreads();
     }
-    // the tile's BK x BK blocks, one row per thread ([block][row][col])
+    // the tile's BK x BK blocks ([block][row][col]): each thread stores the
+    // block row of its slot's row, then one row per thread in row order
     double(*A)[BK][BK + 1] = reinterpret_cast<double(*)[BK][BK + 1]>(buf);
-    const int blk = threadIdx.x / BK, i = threadIdx.x % BK;
+    {
+        const bool rlive = rrow < S.n;
+        const int rb = rk / BK, ri = rk % BK;
 #pragma unroll
-    for (int t = 0; t < BK; t++) A[blk][i][t] = live ? hb[t] : (t == i ? 1.0 : 0.0);
-    if (live) A[blk][i][i] += S.jd[own];
+        for (int t = 0; t < BK; t++) A[rb][ri][t] = rlive ? hb[t] : (t == ri ? 1.0 : 0.0);
+        if (rlive) A[rb][ri][ri] += S.jd[rrow];
+    }
     __syncthreads();
+    const int blk = tid / BK, i = tid % BK;
     // in-place Gauss-Jordan inversion, thread i updates row i
     for (int k = 0; k < BK; k++) {
         const double piv = 1.0 / A[blk][k][k];
@@ -265,11 +329,12 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
         S.m1[own] = m1;
         v[0] = S.r[own] * m1;
         v[1] = (double)own_cnt;
-        v[2] = swide ? (double)own_cnt : 0.0;
+        v[2] = sw[rank / SLICE] ? (double)own_cnt : 0.0;
         v[4] = m1;
     } else if (own < S.npad) {
         S.m1[own] = 0.0;
     }
+    v[3] = slots;
     tile_partials<5>(S, T.row0 / TILE, v, lds);
 }
 
@@ -298,6 +363,7 @@ __global__ void k_fin_w0(const int *seg_ids, Seg *segs)
         st->w = tot[0] / tot[4];
         st->nnz_coul = tot[1];
         st->nnz_wide = tot[2];
+        st->nnz_slots = tot[3];
     }
 }
 
@@ -394,11 +460,11 @@ __device__ __forceinline__ double spmv_row(const double *p, const IDX *row, cons
     return a;
 }
 
-// s = H p and the tile's share of p^T s, one row per lane over the sliced
-// copy; U entries of the row are loaded before their products are summed, so
-// U gathers of p are in flight per lane (U accumulators, combined in a fixed
-// order at the end).  A slice reads 16-bit row offsets (6 bytes per entry)
-// unless it needs the full entries.
+// s = H p and the tile's share of p^T s, one slot (row) per lane over the
+// sliced copy; U entries of the row are loaded before their products are
+// summed, so U gathers of p are in flight per lane (U accumulators, combined
+// in a fixed order at the end).  A slice reads 16-bit row offsets (6 bytes
+// per entry) unless it needs the full entries.
 template <typename R, int U>
 __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
 {
@@ -406,15 +472,16 @@ __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
     const Seg &S = segs[T.seg];
     if (S.sst->done) return;
     __shared__ double lds[4];
-    const int s = T.row0 + threadIdx.x;
+    const int slot = T.row0 + threadIdx.x;
+    const int s = T.row0 + S.hperm[slot];
     double pap = 0.0;
     if (s < S.n) {
-        const size_t b0 = slice_base(s, S.Wl);
+        const size_t b0 = slice_base(slot, S.Wl);
         const R *hrow = reinterpret_cast<const R *>(S.H) + b0;
         const int cnt = S.hcnt[s];
-        const double a = S.swide[s / SLICE]
+        const double a = S.swide[slot / SLICE]
                              ? spmv_row<R, U, uint32_t>(S.p, S.hsidx + b0, hrow, cnt, 0)
-                             : spmv_row<R, U, uint16_t>(S.p, S.hs16 + b0, hrow, cnt, (s & ~(SLICE - 1)) - 32768);
+                             : spmv_row<R, U, uint16_t>(S.p, S.hs16 + b0, hrow, cnt, (slot & ~(SLICE - 1)) - 32768);
         const double ps = S.p[s];
         const double y = S.jd[s] * ps + a;
         S.s[s] = y;

@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Par
     const double4 *xs = S.xs64;
     const double4 li = xs[s];
     const int ti = (int)li.w;
-    const size_t rl = (size_t)s * S.Ws, rb = (size_t)s * S.Wb;
+    const size_t rl = (size_t)s * S.Ws;
     const int ns = S.scnt[s];
     int nb = 0;
     for (int e = 0; e < ns; e++) {
@@ -182,21 +182,21 @@ __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Par
         uint8_t c = 255;
         if (r2 < P.Sc[pp] * P.Sc[pp]) {
             if (nb < S.Wb) {
-                S.bidx[rb + nb] = ent;
-                S.bsrev[rb + nb] = S.srev[rl + e];
+                S.bidx[sliced(s, nb, S.Wb)] = ent;
+                S.bsrev[sliced(s, nb, S.Wb)] = S.srev[rl + e];
                 c = (uint8_t)nb;
             }
             nb++;
         }
-        S.cmap[rl + e] = c;
+        S.cmap[sliced(s, e, S.Ws)] = c;
     }
     if (nb > S.Wb) {
         atomicOr(&S.sst->status, ST_OVERFLOW);
         nb = S.Wb;
     }
     S.bcnt[s] = nb;
-    V4 *slot = reinterpret_cast<V4 *>(S.slot) + rb;
-    const uint32_t *row = S.bidx + rb;
+    const SRow<V4> slot = srow(reinterpret_cast<V4 *>(S.slot), s, S.Wb);
+    const SRow<const uint32_t> row = srow<const uint32_t>(S.bidx, s, S.Wb);
     double ecov = 0.0;
     for (int e = 0; e < nb; e++) {
         const uint32_t ent = row[e];
@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Par
 // Bond index, in the partner i's row, of the reverse of bond (m, e)
 __device__ __forceinline__ int reverse_bond(const Seg &S, int m, int e, int i)
 {
-    return S.cmap[(size_t)i * S.Ws + S.bsrev[(size_t)m * S.Wb + e]];
+    return S.cmap[sliced(i, S.bsrev[sliced(m, e, S.Wb)], S.Ws)];
 }
 
 // pair-term derivative dV/dr of 1/2 fc (fR - b fA) at fixed b
@@ -271,8 +271,8 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
     const V4 lm = xs[m];
     const int tm = (int)lm.w;
     const int nb = S.bcnt[m];
-    const size_t rb = (size_t)m * S.Wb;
-    const uint32_t *row = S.bidx + rb;
+    const SRow<const uint32_t> row = srow<const uint32_t>(S.bidx, m, S.Wb);
+    const SRow<const V4> slm = srow(slot, m, S.Wb);
     double fx = 0, fy = 0, fz = 0;
     // m as the centre of its own bonds
     for (int e = 0; e < nb; e++) {
@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
         const int pp = tm * 2 + (int)lj.w;
         const R3<R> d = pair_vec<R>(lm, lj, dtab[ent >> CODE_SHIFT]);
         const R r = dev_sqrt(d.x * d.x + d.y * d.y + d.z * d.z), ir = (R)1 / r;
-        const V4 sv = slot[rb + e];
+        const V4 sv = slm[e];
         const R dv = pair_dvdr(P, pp, r, sv.x) * ir;
         R ax = dv * d.x, ay = dv * d.y, az = dv * d.z;
         if (sv.y != (R)0 || sv.z != (R)0) {
@@ -314,11 +314,11 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
         const R3<R> dmi = pair_vec<R>(lm, li, dtab[ent >> CODE_SHIFT]);
         const R r = dev_sqrt(dmi.x * dmi.x + dmi.y * dmi.y + dmi.z * dmi.z), ir = (R)1 / r;
         const R3<R> d = {-dmi.x, -dmi.y, -dmi.z};            // i -> m
-        const size_t ri = (size_t)i * S.Wb;
-        const V4 sv = slot[ri + rv];
+        const SRow<const V4> sli = srow(slot, i, S.Wb);
+        const V4 sv = sli[rv];
         const R dv = pair_dvdr(P, pp, r, sv.x) * ir;
         R ax = -dv * d.x, ay = -dv * d.y, az = -dv * d.z;
-        const uint32_t *rowi = S.bidx + ri;
+        const SRow<const uint32_t> rowi = srow<const uint32_t>(S.bidx, i, S.Wb);
         for (int t = 0; t < ni; t++) {
             if (t == rv) continue;
             const uint32_t ent2 = rowi[t];
@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
                 ay -= sv.y * gj[0].y + sv.z * gj[1].y;
                 az -= sv.y * gj[0].z + sv.z * gj[1].z;
             }
-            const V4 sk = slot[ri + t];                         // bond (i -> k)
+            const V4 sk = sli[t];                               // bond (i -> k)
             if (sk.y != (R)0 || sk.z != (R)0) {
                 // bond (i -> k), environment m: m is the environment atom
                 trip_grad(P, ti, pp, dk, rk, d, r, gj, gk);
