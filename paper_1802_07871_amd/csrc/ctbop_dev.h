@@ -160,7 +160,7 @@ struct Seg {
     double *q, *r, *p, *s, *jd;          // [npad]
     // block-Jacobi preconditioner: the inverse of each diagonal BK x BK block
     // of H (blocks of BK consecutive sorted rows; entry (t, u) of block b at
-    // b*BK*BK + t*BK + u), computed in FP64, symmetrised and stored in FP32
+    // b*BK*BK + t*BK + u), computed in FP32, symmetrised and stored in FP32
     // (so the operator is exactly symmetric); its row sums m1 = M 1 (of the
     // stored entries, FP64) and y = M r
     float *binv;       // [npad * BK]

@@ -197,18 +197,21 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
 // the tile through LDS in chunks of HS_CH entries: HS_CH lanes read a row
 // segment, then each lane writes the chunk of its slot's row as slice columns
 // (both sides touch contiguous memory) and adds the entries whose neighbour
-// lies in the row's own BK-row block to that block row, in list order.  The tile's blocks (J on
-// the diagonal) are then inverted in LDS by Gauss-Jordan elimination (H is
-// SPD, so no pivoting), symmetrised and written with their row sums; the
-// tile's partial sums of r m1 and m1 start the projection.
-constexpr int HS_CH = 16;
+// lies in the row's own BK-row block to that block row, in list order.  The
+// tile's blocks (J on the diagonal) are then inverted in LDS by Gauss-Jordan
+// elimination in FP32 (H is SPD and its blocks well conditioned, so no
+// pivoting; the preconditioner only has to be symmetric positive definite,
+// its accuracy sets the iteration count, not the solution), symmetrised and
+// written with their row sums; the tile's partial sums of r m1 and m1 start
+// the projection.
+constexpr int HS_CH = 8;
 template <typename R>
 __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
 {
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     constexpr int CI_BYTES = TILE * (HS_CH + 1) * 4, CV_BYTES = TILE * (HS_CH + 1) * (int)sizeof(R);
-    constexpr int HB_BYTES = (TILE / BK) * BK * (BK + 1) * 8;
+    constexpr int HB_BYTES = (TILE / BK) * BK * (BK + 1) * 4;
     constexpr int BUF = (CI_BYTES + CV_BYTES > HB_BYTES) ? CI_BYTES + CV_BYTES : HB_BYTES;
     __shared__ __align__(16) unsigned char buf[BUF];
     __shared__ int cnt_lds[TILE];
@@ -258,9 +261,9 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
     const int lane = tid % HS_CH;
     const size_t b0 = slice_base(own, S.Wl);
     const int bbase = rrow & ~(BK - 1);
-    double hb[BK];
+    float hb[BK];
 #pragma unroll
-    for (int t = 0; t < BK; t++) hb[t] = 0.0;
+    for (int t = 0; t < BK; t++) hb[t] = 0.0f;
     for (int E0 = 0; E0 < maxc; E0 += HS_CH) {
         for (int k = tid / HS_CH; k < TILE; k += TILE / HS_CH) {
             const int e = E0 + lane;
@@ -281,28 +284,28 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
             const unsigned col = (unsigned)((int)(ent & J_MASK) - bbase);
             if (col < (unsigned)BK) {
 #pragma unroll
-                for (int t = 0; t < BK; t++) hb[t] += (col == (unsigned)t) ? (double)v : 0.0;
+                for (int t = 0; t < BK; t++) hb[t] += (col == (unsigned)t) ? (float)v : 0.0f;
             }
         }
         __syncthreads();
     }
     // the tile's BK x BK blocks ([block][row][col]): each thread stores the
     // block row of its slot's row, then one row per thread in row order
-    double(*A)[BK][BK + 1] = reinterpret_cast<double(*)[BK][BK + 1]>(buf);
+    float(*A)[BK][BK + 1] = reinterpret_cast<float(*)[BK][BK + 1]>(buf);
     {
         const bool rlive = rrow < S.n;
         const int rb = rk / BK, ri = rk % BK;
 #pragma unroll
-        for (int t = 0; t < BK; t++) A[rb][ri][t] = rlive ? hb[t] : (t == ri ? 1.0 : 0.0);
-        if (rlive) A[rb][ri][ri] += S.jd[rrow];
+        for (int t = 0; t < BK; t++) A[rb][ri][t] = rlive ? hb[t] : (t == ri ? 1.0f : 0.0f);
+        if (rlive) A[rb][ri][ri] += (float)S.jd[rrow];
     }
     __syncthreads();
     const int blk = tid / BK, i = tid % BK;
     // in-place Gauss-Jordan inversion, thread i updates row i
     for (int k = 0; k < BK; k++) {
-        const double piv = 1.0 / A[blk][k][k];
-        const double aik = A[blk][i][k];
-        double rowk[BK];
+        const float piv = 1.0f / A[blk][k][k];
+        const float aik = A[blk][i][k];
+        float rowk[BK];
 #pragma unroll
         for (int t = 0; t < BK; t++) rowk[t] = A[blk][k][t];
         __syncthreads();
@@ -310,7 +313,7 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
 #pragma unroll
             for (int t = 0; t < BK; t++) A[blk][k][t] = (t == k) ? piv : rowk[t] * piv;
         } else {
-            const double f = aik * piv;
+            const float f = aik * piv;
 #pragma unroll
             for (int t = 0; t < BK; t++) A[blk][i][t] = (t == k) ? -f : A[blk][i][t] - f * rowk[t];
         }
@@ -320,7 +323,7 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
     float *bo = S.binv + (size_t)(T.row0 + blk * BK) * BK;
 #pragma unroll
     for (int t = 0; t < BK; t++) {
-        const float b = (float)(0.5 * (A[blk][i][t] + A[blk][t][i]));
+        const float b = 0.5f * (A[blk][i][t] + A[blk][t][i]);
         bo[t * BK + i] = b;
         m1 += (double)b;
     }
