@@ -167,7 +167,7 @@ struct Seg {
     double *m1, *y;    // [npad]
     double *q_state;   // user order charges of the last solve, for the warm start [n]
     double *q_h1, *q_h2, *q_h3;   // the three solves before it (predictor history) [n]
-    double *part;      // [ntile * NPART]
+    double *part;      // [NPART * ntile]: partial k of tile t at k * ntile + t
     SegState *sst;
 };
 
@@ -313,7 +313,7 @@ __device__ __forceinline__ void tile_partials(const Seg &S, int tile_local, doub
     block_sum<K>(v, lds, tot);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < K; k++) S.part[(size_t)tile_local * NPART + k] = tot[k];
+        for (int k = 0; k < K; k++) S.part[(size_t)k * S.ntile + tile_local] = tot[k];
     }
 }
 
@@ -326,9 +326,8 @@ __device__ __forceinline__ void seg_total(const Seg &S, double *lds, double (&ou
 #pragma unroll
     for (int k = 0; k < K; k++) v[k] = 0.0;
     for (int t = threadIdx.x; t < S.ntile; t += TILE) {
-        const double *pp = S.part + (size_t)t * NPART;
 #pragma unroll
-        for (int k = 0; k < K; k++) v[k] += pp[k];
+        for (int k = 0; k < K; k++) v[k] += S.part[(size_t)k * S.ntile + t];
     }
     block_sum<K>(v, lds, out);
 }

@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(TILE) k_fire_kick(const Tile *tiles, Seg *segs
     }
     tile_partials<3>(S, T.row0 / TILE, r, lds);
     const double m = block_max(f2, ldm);
-    if (threadIdx.x == 0) S.part[(size_t)(T.row0 / TILE) * NPART + 3] = m;
+    if (threadIdx.x == 0) S.part[(size_t)3 * S.ntile + T.row0 / TILE] = m;
 }
 
 // out[0..3] = P, |v|^2, |F|^2, max |F_i|^2; out[4] = potential energy;
@@ -254,7 +254,7 @@ __global__ void k_fire_fin(const int *seg_ids, Seg *segs, double *out)
     double tot[3];
     seg_total<3>(S, lds, tot);
     double m = 0.0;
-    for (int t = threadIdx.x; t < S.ntile; t += TILE) m = fmax(m, S.part[(size_t)t * NPART + 3]);
+    for (int t = threadIdx.x; t < S.ntile; t += TILE) m = fmax(m, S.part[(size_t)3 * S.ntile + t]);
     m = block_max(m, ldm);
     if (threadIdx.x == 0) {
         out[0] = tot[0];
