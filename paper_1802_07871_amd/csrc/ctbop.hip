@@ -78,6 +78,11 @@ struct ctbop_ctx {
     std::unordered_map<void *, unsigned long> eval_gen;
     std::atomic<int> servers{0};  // live servers on this context
     int *host_flag = nullptr;    // pinned: done, iters
+    // second stream (default priority) for the covalent terms, which overlap
+    // the Coulomb chain of an evaluation; events fork it off the caller's
+    // stream after the lists and join it back before the Coulomb forces
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // optional per-kernel timing with HIP events on the caller's stream
     int profile = 0;
     std::vector<hipEvent_t> ev_free;
@@ -330,9 +335,15 @@ struct Timed {
 };
 
 // after a stream synchronisation: fold completed event pairs into totals
+// (pairs on another stream that have not completed yet stay pending)
 void ev_harvest(ctbop_ctx *ctx)
 {
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> keep;
     for (auto &p : ctx->ev_pending) {
+        if (hipEventQuery(p.second.second) == hipErrorNotReady) {
+            keep.push_back(p);
+            continue;
+        }
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
             ctx->prof_ms[p.first] += ms;
@@ -341,7 +352,17 @@ void ev_harvest(ctbop_ctx *ctx)
         ctx->ev_free.push_back(p.second.first);
         ctx->ev_free.push_back(p.second.second);
     }
-    ctx->ev_pending.clear();
+    ctx->ev_pending.swap(keep);
+}
+
+// the side stream and its two events, created on first use
+int side_stream(ctbop_ctx *ctx)
+{
+    if (ctx->side) return CTBOP_OK;
+    HIPCHK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+    return CTBOP_OK;
 }
 
 int map_status(int st)
@@ -451,10 +472,22 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
     hipStream_t st = P.st;
     const int *sid = P.dsegid;
     launch_lists<R>(ctx, P, prm, flags);
+    // covalent terms on the side stream: they need only the lists and
+    // overlap the assembly, the charge solve and its host round trips (a
+    // fork after the sliced copy, overlapping the solve only, was slower)
+    int rc = side_stream(ctx);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(ctx->ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
     {
-        Timed t(ctx, 3, st);
-        hipLaunchKernelGGL((k_bond<R>), g, b, 0, st, P.dtiles, P.dseg, ctx->pd);
+        Timed t(ctx, 3, ctx->side);
+        hipLaunchKernelGGL((k_bond<R>), g, b, 0, ctx->side, P.dtiles, P.dseg, ctx->pd);
     }
+    {
+        Timed t(ctx, 4, ctx->side);
+        hipLaunchKernelGGL((k_force_cov<R>), g, b, 0, ctx->side, P.dtiles, P.dseg, prm, 0);
+    }
+    HIPCHK(hipEventRecord(ctx->ev_join, ctx->side));
     CgCtl ctl{ctx->opts.cg_tol, ctx->opts.cg_maxit};
     {
         Timed t(ctx, 2, st);
@@ -498,10 +531,7 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
     }
     ctx->last_iters[P.base] = ctx->host_flag[1];
     if (iters_out) *iters_out = ctx->host_flag[1];
-    {
-        Timed t(ctx, 4, st);
-        hipLaunchKernelGGL((k_force_cov<R>), g, b, 0, st, P.dtiles, P.dseg, prm, 0);
-    }
+    HIPCHK(hipStreamWaitEvent(st, ctx->ev_join, 0));
     {
         Timed t(ctx, 1, st);
         hipLaunchKernelGGL((k_force_coul<R, LPR>), g, b, 0, st, P.dtiles, P.dseg, ctx->pd, 0);
@@ -628,6 +658,12 @@ int ctbop_set_params(ctbop_ctx *ctx, const double *params, int n_params)
 int ctbop_destroy(ctbop_ctx *ctx)
 {
     if (!ctx) return CTBOP_OK;
+    if (ctx->side) {
+        (void)hipStreamSynchronize(ctx->side);
+        (void)hipStreamDestroy(ctx->side);
+        (void)hipEventDestroy(ctx->ev_fork);
+        (void)hipEventDestroy(ctx->ev_join);
+    }
     if (ctx->host_flag) (void)hipHostFree(ctx->host_flag);
     for (auto e : ctx->ev_free) (void)hipEventDestroy(e);
     for (auto &p : ctx->ev_pending) {

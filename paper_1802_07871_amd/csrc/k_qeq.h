@@ -505,7 +505,7 @@ __global__ void k_fin_alpha(const int *seg_ids, Seg *segs)
     if (threadIdx.x == 0) {
         SegState *st = S.sst;
         if (!(tot[0] > 0.0)) {
-            st->status |= ST_NOT_PD;
+            atomicOr(&st->status, ST_NOT_PD);
             st->done = 1;
             st->alpha = 0.0;
         } else {
@@ -566,7 +566,7 @@ __global__ void k_fin_update(const int *seg_ids, Seg *segs, CgCtl ctl)
         st->iters_total += 1;
         st->qshift = (S.Q - tot[4]) / S.n;
         if (st->res < ctl.tol) st->done = 1;
-        else if (st->iters >= ctl.maxit) { st->done = 1; st->status |= ST_NOCONV; }
+        else if (st->iters >= ctl.maxit) { st->done = 1; atomicOr(&st->status, ST_NOCONV); }
     }
 }
 
