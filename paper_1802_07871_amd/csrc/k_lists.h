@@ -114,30 +114,24 @@ __global__ void k_scan(const int *seg_ids, Seg *segs)
 {
     const Seg &S = segs[seg_ids[blockIdx.x]];
     if (!S.sst->rebuild) return;
-    __shared__ int lds[TILE];
-    __shared__ int carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int base = 0; base < S.ncell; base += TILE) {
-        int c = base + threadIdx.x;
-        int v = c < S.ncell ? S.cell_cnt[c] : 0;
-        lds[threadIdx.x] = v;
-        __syncthreads();
-        for (int o = 1; o < TILE; o <<= 1) {          // Hillis-Steele inclusive scan
-            int a = threadIdx.x >= o ? lds[threadIdx.x - o] : 0;
-            __syncthreads();
-            lds[threadIdx.x] += a;
-            __syncthreads();
-        }
-        if (c < S.ncell) {
-            S.cell_start[c] = carry + lds[threadIdx.x] - v;
-            S.cell_cnt[c] = 0;
-        }
-        __syncthreads();
-        if (threadIdx.x == TILE - 1) carry += lds[TILE - 1];
-        __syncthreads();
+    __shared__ int lds[4];
+    // each thread scans one contiguous run of cells: its run's total, the
+    // block's exclusive scan of the totals, then the run's starts
+    const int per = (S.ncell + TILE - 1) / TILE;
+    const int c0 = min(S.ncell, (int)threadIdx.x * per), c1 = min(S.ncell, c0 + per);
+    int sum = 0;
+#pragma unroll 16
+    for (int c = c0; c < c1; c++) sum += S.cell_cnt[c];
+    int run = block_excl_scan(sum, lds);
+#pragma unroll 16
+    for (int c = c0; c < c1; c++) {
+        const int v = S.cell_cnt[c];
+        S.cell_start[c] = run;
+        S.cell_cnt[c] = 0;
+        run += v;
     }
-    if (threadIdx.x == 0) S.cell_start[S.ncell] = carry;
+    // the last thread's run ends at the total (trailing runs may be empty)
+    if (threadIdx.x == TILE - 1) S.cell_start[S.ncell] = run;
 }
 
 __global__ void k_scatter(const Tile *tiles, Seg *segs)
@@ -306,19 +300,30 @@ __global__ void __launch_bounds__(TILE) k_build(const Tile *tiles, Seg *segs, Pa
                 int e1 = c1 + d1;
                 if (S.pbc[1]) { e1 %= S.nb[1]; if (e1 < 0) e1 += S.nb[1]; }
                 else if (e1 < 0 || e1 >= S.nb[1]) continue;
-                for (int d2 = -S.st[2]; d2 <= S.st[2]; d2++) {
-                    int e2 = c2 + d2;
-                    if (S.pbc[2]) { e2 %= S.nb[2]; if (e2 < 0) e2 += S.nb[2]; }
-                    else if (e2 < 0 || e2 >= S.nb[2]) continue;
-                    const int code = code_of(d0, d1, d2);
-                    const V4 D = dtab[code];
-                    const int cc = (e0 * S.nb[1] + e1) * S.nb[2] + e2;
-                    const int m0 = S.cell_start[cc], m1 = S.cell_start[cc + 1];
+                // The cells of one stencil row along the last axis are
+                // consecutive, and so are their atoms: the lanes walk each
+                // run of cells that does not cross the periodic seam as one
+                // range (in the same order as cell by cell), and each lane
+                // takes its atom's offset from the atom's cell.
+                const int rowc = (e0 * S.nb[1] + e1) * S.nb[2];
+                int dlo = -S.st[2], dhi = S.st[2];
+                if (!S.pbc[2]) {
+                    dlo = max(dlo, -c2);
+                    dhi = min(dhi, S.nb[2] - 1 - c2);
+                }
+                for (int dr = dlo; dr <= dhi;) {
+                    int er = c2 + dr;
+                    if (S.pbc[2]) { er %= S.nb[2]; if (er < 0) er += S.nb[2]; }
+                    const int len = min(dhi - dr + 1, S.nb[2] - er);
+                    const int m0 = S.cell_start[rowc + er], m1 = S.cell_start[rowc + er + len];
                     for (int mb = m0; mb < m1; mb += L) {
                         const int m = mb + lane;
                         bool inl = false, ins = false;
                         uint32_t ent = 0;
+                        const int d2 = m < m1 ? dr + (S.csort[m] - rowc - er) : 0;
+                        const int code = code_of(d0, d1, d2);
                         if (m < m1 && !(m == s && code == CODE_CENTER)) {
+                            const V4 D = dtab[code];
                             const V4 lj = xs[m];
                             R rx = (lj.x - li.x) + D.x, ry = (lj.y - li.y) + D.y, rz = (lj.z - li.z) + D.z;
                             float r2 = (float)(rx * rx + ry * ry + rz * rz);
@@ -341,6 +346,7 @@ __global__ void __launch_bounds__(TILE) k_build(const Tile *tiles, Seg *segs, Pa
                         nl += __popc(gl);
                         ns += __popc(gs);
                     }
+                    dr += len;
                 }
             }
         }
