@@ -191,7 +191,7 @@ static int nl_cells_sel(const cell_t *c, int n, const double *pos, double rc, nl
     }
     for (long k = 0; k < ncell; k++) head[k + 1] += head[k];
     int *members = malloc(sizeof(int) * n);
-    long *fill = calloc(ncell, sizeof(long));
+    long *fill = calloc((size_t)ncell + 1, sizeof(long));
     for (int i = 0; i < n; i++) members[head[cid[i]] + fill[cid[i]]++] = i;
     free(fill);
 
