@@ -450,13 +450,15 @@ __device__ __forceinline__ double spmv_row(const double *p, const IDX *row, cons
         R hh[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            jj[u] = row[(size_t)(e + u) * SLICE];
-            hh[u] = hrow[(size_t)(e + u) * SLICE];
+            jj[u] = __builtin_nontemporal_load(row + (size_t)(e + u) * SLICE);
+            hh[u] = __builtin_nontemporal_load(hrow + (size_t)(e + u) * SLICE);
         }
 #pragma unroll
         for (int u = 0; u < U; u++) acc[u] += (double)hh[u] * p[jbase + (int)(jj[u] & J_MASK)];
     }
-    for (; e < cnt; e++) acc[0] += (double)hrow[(size_t)e * SLICE] * p[jbase + (int)(row[(size_t)e * SLICE] & J_MASK)];
+    for (; e < cnt; e++)
+        acc[0] += (double)__builtin_nontemporal_load(hrow + (size_t)e * SLICE) *
+                  p[jbase + (int)(__builtin_nontemporal_load(row + (size_t)e * SLICE) & J_MASK)];
     double a = 0.0;
 #pragma unroll
     for (int u = 0; u < U; u++) a += acc[u];
