@@ -34,9 +34,16 @@
  *   ownership  every device byte is the caller's: inputs, outputs and the
  *              per-system buffer `sys` (lists, charges for the warm start,
  *              scratch).  The library never allocates device memory.  A
- *              context holds only host-side parameters and options.
+ *              context holds host-side parameters and options, a pinned
+ *              host word pair for the solver's flag and, from its first
+ *              evaluation on, one stream of its own (default priority) with
+ *              two events.
  *   streams    every call enqueues work on the caller's stream (hipStream_t
- *              passed as void*, NULL = default stream).  The charge solve
+ *              passed as void*, NULL = default stream).  An evaluation forks
+ *              its covalent kernels onto the context's stream after the
+ *              neighbour lists and joins them back (an event wait on the
+ *              caller's stream) before the Coulomb forces, so the caller's
+ *              stream orders every result as usual.  The charge solve
  *              stops on a device-side test, so the host waits on that stream
  *              between batches of solver iterations (cg_check) to read the
  *              flag; with info != NULL it also waits at the end to report.
