@@ -240,7 +240,7 @@ int ctbop_md_run_nvt(ctbop_ctx *ctx, int n, double *x_dev, double *v_dev, const 
  * such steps in a row dt <- min(f_inc dt, dtmax_fs) and alpha <- f_alpha
  * alpha; if P <= 0, dt <- f_dec dt, v <- 0, alpha <- alpha_start.  Fixed
  * atoms (fixed_dev != 0) neither move nor count.  Charges are re-equilibrated
- * at every step (warm start, no time extrapolation).
+ * at every step (warm start from the extrapolation of the last solutions).
  *   x_dev        double[3n] SoA positions (device, in/out)
  *   v_dev        double[3n] device velocity workspace (zeroed on entry)
  *   E_trace_host NULL or max_steps + 1 doubles: the energy after step s
