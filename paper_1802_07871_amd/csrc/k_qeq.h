@@ -194,34 +194,51 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
 // Sliced copy (hsidx, H) of the step's rows (hidx, Hr) for the charge-solve
 // product, and the block-Jacobi preconditioner.  Each block first orders its
 // tile's rows by decreasing length (the slot order, hperm), then transposes
-// the tile through LDS in chunks of HS_CH entries: HS_CH lanes read a row
-// segment, then each lane writes the chunk of its slot's row as slice columns
-// (both sides touch contiguous memory) and adds the entries whose neighbour
-// lies in the row's own BK-row block to that block row, in list order.  The
-// tile's blocks (J on the diagonal) are then inverted in LDS by Gauss-Jordan
+// the tile one slice (SLICE slots) at a time through LDS, in chunks of HS_CH
+// entries per row: four lanes read one row's chunk as whole 128-byte lines
+// of hidx and Hr, and add the entries whose neighbour lies in the row's own
+// BK-row block to their part of that block row; then every lane writes
+// entries of its slot as slice columns (64 lanes store contiguous memory).
+// The four parts of each block row are added in a fixed order.  The tile's
+// blocks (J on the diagonal) are then inverted in LDS by Gauss-Jordan
 // elimination in FP32 (H is SPD and its blocks well conditioned, so no
 // pivoting; the preconditioner only has to be symmetric positive definite,
 // its accuracy sets the iteration count, not the solution), symmetrised and
 // written with their row sums; the tile's partial sums of r m1 and m1 start
 // the projection.
-constexpr int HS_CH = 8;
+constexpr int HS_CH = 32;                // entries per row and chunk (4 lanes x 8)
+constexpr int HS_LPR = 4;                // lanes reading one row's chunk
+
+// entries e0 .. e0+7 of a row-major row (fewer when the row ends first)
+template <typename T>
+__device__ __forceinline__ void load8(const T *row, int e0, int cnt, bool vec, T (&out)[8])
+{
+    if (vec && e0 + 8 <= cnt) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(row + e0);
+        uint4 w[8 * sizeof(T) / 16];
+#pragma unroll
+        for (int k = 0; k < (int)(8 * sizeof(T) / 16); k++) w[k] = src[k];
+        memcpy(out, w, sizeof out);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; k++) out[k] = e0 + k < cnt ? row[e0 + k] : (T)0;
+    }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
 {
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
-    constexpr int CI_BYTES = TILE * (HS_CH + 1) * 4, CV_BYTES = TILE * (HS_CH + 1) * (int)sizeof(R);
-    constexpr int HB_BYTES = (TILE / BK) * BK * (BK + 1) * 4;
-    constexpr int BUF = (CI_BYTES + CV_BYTES > HB_BYTES) ? CI_BYTES + CV_BYTES : HB_BYTES;
-    __shared__ __align__(16) unsigned char buf[BUF];
+    __shared__ uint32_t ci[SLICE][HS_CH + 1];
+    __shared__ R cv[SLICE][HS_CH + 1];
+    __shared__ float A[TILE / BK][BK][BK + 1];
     __shared__ int cnt_lds[TILE];
-    __shared__ int mx[4];
-    __shared__ double lds[4 * 5];
-    uint32_t(*ci)[HS_CH + 1] = reinterpret_cast<uint32_t(*)[HS_CH + 1]>(buf);
-    R(*cv)[HS_CH + 1] = reinterpret_cast<R(*)[HS_CH + 1]>(buf + CI_BYTES);
     __shared__ int slot_row[TILE];
+    __shared__ int slot_cnt[TILE];
     __shared__ uint8_t wide_row[TILE];
     __shared__ uint8_t sw[TILE / SLICE];
+    __shared__ double lds[4 * 5];
     const int tid = threadIdx.x;
     const int own = T.row0 + tid;
     const bool live = own < S.n;
@@ -236,68 +253,98 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
         rank += (c > own_cnt || (c == own_cnt && k < tid)) ? 1 : 0;
     }
     slot_row[rank] = tid;
+    slot_cnt[rank] = own_cnt;
     __syncthreads();
-    // from here to the block assembly, thread tid works on slot tid (row rk);
-    // a wave is a slice: the 16-bit form unless one of its rows needs the full one
+    // thread tid's slot is tid (row rk); a wave is a slice: the 16-bit form
+    // unless one of its rows needs the full one
     const int rk = slot_row[tid];
     const int rrow = T.row0 + rk;
-    const int rcnt = cnt_lds[rk];
     S.hperm[own] = (uint8_t)rk;
     const bool swide = __ballot(wide_row[rk] != 0) != 0ull;
     if ((tid & (SLICE - 1)) == 0) {
         S.swide[own / SLICE] = swide ? 1 : 0;
         sw[tid / SLICE] = swide ? 1 : 0;
     }
-    const int sbase = own & ~(SLICE - 1);
-    int m = rcnt;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
-    if ((tid & 63) == 0) mx[tid >> 6] = m;
-    const double slots = (tid & (SLICE - 1)) == 0 ? (double)(SLICE * m) : 0.0;
-    __syncthreads();
-    const int maxc = max(max(mx[0], mx[1]), max(mx[2], mx[3]));
+    // slots padded to the slice's longest row (its first slot)
+    const double slots = (tid & (SLICE - 1)) == 0 ? (double)SLICE * (double)slot_cnt[tid] : 0.0;
+    __syncthreads();                         // every slice's form (sw) is set
     const R *Hr = reinterpret_cast<const R *>(S.Hr);
     R *H = reinterpret_cast<R *>(S.H);
-    const int lane = tid % HS_CH;
-    const size_t b0 = slice_base(own, S.Wl);
-    const int bbase = rrow & ~(BK - 1);
-    float hb[BK];
+    const bool vec = (S.Wl & 3) == 0;        // rows start on 16-byte boundaries
+    for (int sl = 0; sl < TILE / SLICE; sl++) {
+        const int slot0 = sl * SLICE;
+        const int sbase = T.row0 + slot0;
+        const int mlen = slot_cnt[slot0];
+        const bool wide = sw[sl] != 0;
+        // reading: lanes 4l .. 4l+3 take slot l's row
+        const int rl = tid / HS_LPR, rq = tid % HS_LPR;
+        const int rrk = slot_row[slot0 + rl];
+        const int rcnt = slot_cnt[slot0 + rl];
+        const int rbb = (T.row0 + rrk) & ~(BK - 1);
+        const uint32_t *irow = S.hidx + (size_t)(T.row0 + rrk) * S.Wl;
+        const R *vrow = Hr + (size_t)(T.row0 + rrk) * S.Wl;
+        // writing: lane l of wave w takes entries w, w+4, ... of slot l's chunk
+        const int wl = tid % SLICE, wq = tid / SLICE;
+        const int wcnt = slot_cnt[slot0 + wl];
+        const size_t b0 = slice_base(sbase + wl, S.Wl);
+        float hb[BK];
 #pragma unroll
-    for (int t = 0; t < BK; t++) hb[t] = 0.0f;
-    for (int E0 = 0; E0 < maxc; E0 += HS_CH) {
-        for (int k = tid / HS_CH; k < TILE; k += TILE / HS_CH) {
-            const int e = E0 + lane;
-            if (e < cnt_lds[k]) {
-                const size_t at = (size_t)(T.row0 + k) * S.Wl + e;
-                ci[k][lane] = S.hidx[at];
-                cv[k][lane] = Hr[at];
-            }
-        }
-        __syncthreads();
-        const int lim = min(HS_CH, rcnt - E0);
-        for (int e = 0; e < lim; e++) {
-            const uint32_t ent = ci[rk][e];
-            const R v = cv[rk][e];
-            if (swide) S.hsidx[b0 + (size_t)(E0 + e) * SLICE] = ent;
-            else S.hs16[b0 + (size_t)(E0 + e) * SLICE] = (uint16_t)((int)(ent & J_MASK) - sbase + 32768);
-            H[b0 + (size_t)(E0 + e) * SLICE] = v;
-            const unsigned col = (unsigned)((int)(ent & J_MASK) - bbase);
-            if (col < (unsigned)BK) {
+        for (int t = 0; t < BK; t++) hb[t] = 0.0f;
+        for (int E0 = 0; E0 < mlen; E0 += HS_CH) {
+            const int e0 = E0 + rq * 8;
+            if (e0 < rcnt) {
+                uint32_t ie[8];
+                R ve[8];
+                load8(irow, e0, rcnt, vec, ie);
+                load8(vrow, e0, rcnt, vec, ve);
 #pragma unroll
-                for (int t = 0; t < BK; t++) hb[t] += (col == (unsigned)t) ? (float)v : 0.0f;
+                for (int k = 0; k < 8; k++) {
+                    ci[rl][rq * 8 + k] = ie[k];
+                    cv[rl][rq * 8 + k] = ve[k];
+                    const unsigned col = (unsigned)((int)(ie[k] & J_MASK) - rbb);
+                    if (e0 + k < rcnt && col < (unsigned)BK) {
+#pragma unroll
+                        for (int t = 0; t < BK; t++) hb[t] += (col == (unsigned)t) ? (float)ve[k] : 0.0f;
+                    }
+                }
             }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < HS_CH / 4; k++) {
+                const int c = wq + 4 * k;
+                const int e = E0 + c;
+                if (e < wcnt) {
+                    const uint32_t ent = ci[wl][c];
+                    if (wide) S.hsidx[b0 + (size_t)e * SLICE] = ent;
+                    else S.hs16[b0 + (size_t)e * SLICE] = (uint16_t)((int)(ent & J_MASK) - sbase + 32768);
+                    H[b0 + (size_t)e * SLICE] = cv[wl][c];
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
+        // the slot's block row: the four readers' parts, added pairwise
+#pragma unroll
+        for (int t = 0; t < BK; t++) {
+            hb[t] += __shfl_xor(hb[t], 1, 64);
+            hb[t] += __shfl_xor(hb[t], 2, 64);
+        }
+        if (rq == 0) {
+#pragma unroll
+            for (int t = 0; t < BK; t++) A[rrk / BK][rrk % BK][t] = hb[t];
+        }
     }
-    // the tile's BK x BK blocks ([block][row][col]): each thread stores the
-    // block row of its slot's row, then one row per thread in row order
-    float(*A)[BK][BK + 1] = reinterpret_cast<float(*)[BK][BK + 1]>(buf);
+    __syncthreads();
+    // the tile's BK x BK blocks ([block][row][col]) hold the block rows; add
+    // J on the diagonal (identity rows past n), then one row per thread in row order
     {
         const bool rlive = rrow < S.n;
         const int rb = rk / BK, ri = rk % BK;
+        if (rlive) {
+            A[rb][ri][ri] += (float)S.jd[rrow];
+        } else {
 #pragma unroll
-        for (int t = 0; t < BK; t++) A[rb][ri][t] = rlive ? hb[t] : (t == ri ? 1.0f : 0.0f);
-        if (rlive) A[rb][ri][ri] += (float)S.jd[rrow];
+            for (int t = 0; t < BK; t++) A[rb][ri][t] = (t == ri ? 1.0f : 0.0f);
+        }
     }
     __syncthreads();
     const int blk = tid / BK, i = tid % BK;
