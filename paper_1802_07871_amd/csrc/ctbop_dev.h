@@ -215,6 +215,47 @@ template <typename T> struct SRow {
 };
 template <typename T> __device__ __forceinline__ SRow<T> srow(T *a, int s, int W) { return SRow<T>{a + slice_base(s, W)}; }
 
+// The same pointer in the global address space.  Pointers read from a Seg
+// are generic, so their loads compile to flat instructions, which count on
+// both the vector-memory and the LDS counters: every wait for one then waits
+// for the other, and loads issued ahead cannot stay in flight across LDS
+// traffic.  Global loads count on the vector-memory counter only.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gbl(const T *p)
+{
+    return (const __attribute__((address_space(1))) T *)p;
+}
+template <typename T> __device__ __forceinline__ __attribute__((address_space(1))) T *gblw(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+
+// element i of an array of float4/double4, loaded as one global vector load
+template <typename R> struct NVec4;
+template <> struct NVec4<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct NVec4<double> { typedef double type __attribute__((ext_vector_type(4))); };
+template <typename R>
+__device__ __forceinline__ typename Vec4<R>::type ld4(const typename Vec4<R>::type *p, size_t i)
+{
+    const typename NVec4<R>::type v = ((const __attribute__((address_space(1))) typename NVec4<R>::type *)p)[i];
+    typename Vec4<R>::type o;
+    o.x = v.x;
+    o.y = v.y;
+    o.z = v.z;
+    o.w = v.w;
+    return o;
+}
+template <typename R>
+__device__ __forceinline__ void st4(typename Vec4<R>::type *p, size_t i, const typename Vec4<R>::type &o)
+{
+    typename NVec4<R>::type v;
+    v.x = o.x;
+    v.y = o.y;
+    v.z = o.z;
+    v.w = o.w;
+    ((__attribute__((address_space(1))) typename NVec4<R>::type *)p)[i] = v;
+}
+
 __device__ __forceinline__ int code_of(int d0, int d1, int d2) { return ((d0 + 3) * 7 + (d1 + 3)) * 7 + (d2 + 3); }
 
 // reverse offset code: (-d0, -d1, -d2)
@@ -325,9 +366,14 @@ __device__ __forceinline__ void seg_total(const Seg &S, double *lds, double (&ou
     double v[K];
 #pragma unroll
     for (int k = 0; k < K; k++) v[k] = 0.0;
-    for (int t = threadIdx.x; t < S.ntile; t += TILE) {
+    // unrolled so that the loads of several rounds are in flight together
+    // (the sums still take the tiles in order)
+    const auto part = gbl(S.part);
+    const int nt = S.ntile;
+#pragma unroll 8
+    for (int t = threadIdx.x; t < nt; t += TILE) {
 #pragma unroll
-        for (int k = 0; k < K; k++) v[k] += S.part[(size_t)k * S.ntile + t];
+        for (int k = 0; k < K; k++) v[k] += part[(size_t)k * nt + t];
     }
     block_sum<K>(v, lds, out);
 }

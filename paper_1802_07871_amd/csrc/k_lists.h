@@ -277,54 +277,61 @@ __global__ void __launch_bounds__(TILE) k_build(const Tile *tiles, Seg *segs, Pa
     __shared__ int red[4][5];
     load_dtab<R>(S, dtab);
     const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
+    // the segment's fields in registers: the list stores below cannot change them
+    const int Wl = S.Wl, Ws = S.Ws, n = S.n;
+    const int nb0 = S.nb[0], nb1 = S.nb[1], nb2 = S.nb[2];
+    const int st0 = S.st[0], st1 = S.st[1], st2 = S.st[2];
+    const bool pbc0 = S.pbc[0], pbc1 = S.pbc[1], pbc2 = S.pbc[2];
+    const auto csort = gbl(S.csort);
+    const auto cstart = gbl(S.cell_start);
     constexpr int G = TILE / L;
     const int lane = threadIdx.x % L;
     const unsigned below = (1u << lane) - 1u;
     int st_or = 0, mx_l = 0, mx_s = 0, sum_l = 0, sum_s = 0;
     for (int k = threadIdx.x / L; k < TILE; k += G) {
         const int s = T.row0 + k;
-        if (s >= S.n) continue;                // the whole group skips together
-        const V4 li = xs[s];
+        if (s >= n) continue;                  // the whole group skips together
+        const V4 li = ld4<R>(xs, s);
         const int ti = (int)li.w;
-        const int c = S.csort[s];
-        const int c0 = c / (S.nb[1] * S.nb[2]), c1 = (c / S.nb[2]) % S.nb[1], c2 = c % S.nb[2];
-        uint32_t *lrow = S.lidx + (size_t)s * S.Wl;
-        uint32_t *srow = S.sidx + (size_t)s * S.Ws;
+        const int c = csort[s];
+        const int c0 = c / (nb1 * nb2), c1 = (c / nb2) % nb1, c2 = c % nb2;
+        const auto lrow = gblw(S.lidx + (size_t)s * Wl);
+        const auto srow = gblw(S.sidx + (size_t)s * Ws);
         int nl = 0, ns = 0;
         bool close = false;
-        for (int d0 = -S.st[0]; d0 <= S.st[0]; d0++) {
+        for (int d0 = -st0; d0 <= st0; d0++) {
             int e0 = c0 + d0;
-            if (S.pbc[0]) { e0 %= S.nb[0]; if (e0 < 0) e0 += S.nb[0]; }
-            else if (e0 < 0 || e0 >= S.nb[0]) continue;
-            for (int d1 = -S.st[1]; d1 <= S.st[1]; d1++) {
+            if (pbc0) { e0 %= nb0; if (e0 < 0) e0 += nb0; }
+            else if (e0 < 0 || e0 >= nb0) continue;
+            for (int d1 = -st1; d1 <= st1; d1++) {
                 int e1 = c1 + d1;
-                if (S.pbc[1]) { e1 %= S.nb[1]; if (e1 < 0) e1 += S.nb[1]; }
-                else if (e1 < 0 || e1 >= S.nb[1]) continue;
+                if (pbc1) { e1 %= nb1; if (e1 < 0) e1 += nb1; }
+                else if (e1 < 0 || e1 >= nb1) continue;
                 // The cells of one stencil row along the last axis are
                 // consecutive, and so are their atoms: the lanes walk each
                 // run of cells that does not cross the periodic seam as one
                 // range (in the same order as cell by cell), and each lane
                 // takes its atom's offset from the atom's cell.
-                const int rowc = (e0 * S.nb[1] + e1) * S.nb[2];
-                int dlo = -S.st[2], dhi = S.st[2];
-                if (!S.pbc[2]) {
+                const int rowc = (e0 * nb1 + e1) * nb2;
+                int dlo = -st2, dhi = st2;
+                if (!pbc2) {
                     dlo = max(dlo, -c2);
-                    dhi = min(dhi, S.nb[2] - 1 - c2);
+                    dhi = min(dhi, nb2 - 1 - c2);
                 }
                 for (int dr = dlo; dr <= dhi;) {
                     int er = c2 + dr;
-                    if (S.pbc[2]) { er %= S.nb[2]; if (er < 0) er += S.nb[2]; }
-                    const int len = min(dhi - dr + 1, S.nb[2] - er);
-                    const int m0 = S.cell_start[rowc + er], m1 = S.cell_start[rowc + er + len];
+                    if (pbc2) { er %= nb2; if (er < 0) er += nb2; }
+                    const int len = min(dhi - dr + 1, nb2 - er);
+                    const int m0 = cstart[rowc + er], m1 = cstart[rowc + er + len];
                     for (int mb = m0; mb < m1; mb += L) {
                         const int m = mb + lane;
                         bool inl = false, ins = false;
                         uint32_t ent = 0;
-                        const int d2 = m < m1 ? dr + (S.csort[m] - rowc - er) : 0;
+                        const int d2 = m < m1 ? dr + (csort[m] - rowc - er) : 0;
                         const int code = code_of(d0, d1, d2);
                         if (m < m1 && !(m == s && code == CODE_CENTER)) {
                             const V4 D = dtab[code];
-                            const V4 lj = xs[m];
+                            const V4 lj = ld4<R>(xs, m);
                             R rx = (lj.x - li.x) + D.x, ry = (lj.y - li.y) + D.y, rz = (lj.z - li.z) + D.z;
                             float r2 = (float)(rx * rx + ry * ry + rz * rz);
                             if (r2 < P.l_cut2) {
@@ -337,11 +344,11 @@ __global__ void __launch_bounds__(TILE) k_build(const Tile *tiles, Seg *segs, Pa
                         const unsigned gl = group_ballot<L>(inl), gs = group_ballot<L>(ins);
                         if (inl) {
                             const int at = nl + __popc(gl & below);
-                            if (at < S.Wl) lrow[at] = ent;
+                            if (at < Wl) lrow[at] = ent;
                         }
                         if (ins) {
                             const int at = ns + __popc(gs & below);
-                            if (at < S.Ws) srow[at] = ent;
+                            if (at < Ws) srow[at] = ent;
                         }
                         nl += __popc(gl);
                         ns += __popc(gs);
@@ -353,8 +360,8 @@ __global__ void __launch_bounds__(TILE) k_build(const Tile *tiles, Seg *segs, Pa
         const bool any_close = group_ballot<L>(close) != 0u;
         if (lane == 0) {
             if (any_close) st_or |= ST_TOO_CLOSE;
-            if (nl > S.Wl || ns > S.Ws) st_or |= ST_OVERFLOW;
-            const int cl = nl < S.Wl ? nl : S.Wl, cs = ns < S.Ws ? ns : S.Ws;
+            if (nl > Wl || ns > Ws) st_or |= ST_OVERFLOW;
+            const int cl = nl < Wl ? nl : Wl, cs = ns < Ws ? ns : Ws;
             S.lcnt[s] = cl;
             S.scnt[s] = cs;
             mx_l = max(mx_l, nl);

@@ -42,26 +42,37 @@ __device__ __forceinline__ double rcbrt64(double u)
     return y * (4.0 - u * y * y * y) * (1.0 / 3.0);
 }
 
-__device__ __forceinline__ double coul64(const Params<double> &P, int pp, double r, double &dCr)
+// g3 = gamma_ij^-3 of the pair
+__device__ __forceinline__ double coul64_g(const Params<double> &P, double g3, double r, double &dCr)
 {
     const double x = r * P.inv_rc, x2 = x * x, x3 = x2 * x;
     const double om = 1.0 - x, om2 = om * om;
     const double T = om2 * om2 * (1.0 + 4.0 * x + 10.0 * x2 + 20.0 * x3);
-    const double u = r * r * r + P.g3[pp];
+    const double u = r * r * r + g3;
     const double y = rcbrt64(u);
     const double y2 = y * y;
     dCr = P.ke * (-140.0 * P.inv_rc * P.inv_rc * x2 * om2 * om * y - T * r * y2 * y2);
     return P.ke * T * y;
 }
 
-__device__ __forceinline__ double coul64_val(const Params<double> &P, int pp, double r)
+__device__ __forceinline__ double coul64(const Params<double> &P, int pp, double r, double &dCr)
+{
+    return coul64_g(P, P.g3[pp], r, dCr);
+}
+
+__device__ __forceinline__ double coul64_val_g(const Params<double> &P, double g3, double r)
 {
     const double x = r * P.inv_rc, x2 = x * x, x3 = x2 * x;
     const double om = 1.0 - x, om2 = om * om;
     const double T = om2 * om2 * (1.0 + 4.0 * x + 10.0 * x2 + 20.0 * x3);
-    const double u = r * r * r + P.g3[pp];
+    const double u = r * r * r + g3;
     const double y = rcbrt64(u);
     return P.ke * T * y;
+}
+
+__device__ __forceinline__ double coul64_val(const Params<double> &P, int pp, double r)
+{
+    return coul64_val_g(P, P.g3[pp], r);
 }
 
 struct CgCtl {
@@ -92,6 +103,7 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
     __shared__ V4 dtab[NCODE];
     load_dtab2<R>(S, dtab);
     const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
+    const auto qv = gbl(S.q);
     R *Hr = reinterpret_cast<R *>(S.Hr);
     const double mprev = S.sst->mu_prev;
     constexpr int G = TILE / LPR;
@@ -116,10 +128,11 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
         }
         const V4 li = xs[s];
         const int ti = (int)li.w;
+        const double g3_0 = PD.g3[ti * 2], g3_1 = PD.g3[ti * 2 + 1];
         const int cnt = S.lcnt[s];
-        const uint32_t *row = S.lidx + (size_t)s * S.Wl;
-        uint32_t *hrow = S.hidx + (size_t)s * S.Wl;
-        R *vrow = Hr + (size_t)s * S.Wl;
+        const auto row = gbl(S.lidx + (size_t)s * S.Wl);
+        const auto hrow = gblw(S.hidx + (size_t)s * S.Wl);
+        const auto vrow = gblw(Hr + (size_t)s * S.Wl);
         double acc = 0.0;
         int nbuf = 0, done = 0;
         bool wide = false;
@@ -129,26 +142,29 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
             bool in = false;
             uint32_t ent = 0;
             int j = 0, tj = 0;
-            double r = 0.0;
+            double r = 0.0, qj = 0.0;
             if (e < cnt) {
                 ent = row[e];
                 j = (int)(ent & J_MASK);
-                const V4 lj = xs[j];
+                const V4 lj = ld4<R>(xs, j);
+                qj = qv[j];                      // loaded beside the position (most entries are kept)
                 tj = (int)lj.w;
                 R3<R> d;
                 r = entry_r<R>(li, lj, dtab[ent >> CODE_SHIFT], d);
                 in = r < PD.rc;
             }
             const unsigned gm = group_ballot<LPR>(in);
+            double cv = 0.0;
             if (in) {
                 const int at = nbuf + __popc(gm & below);
-                const R c = (R)coul64_val(PD, ti * 2 + tj, r);
+                const R c = (R)coul64_val_g(PD, tj ? g3_1 : g3_0, r);
                 bi[at] = ent;
                 bv[at] = c;
-                acc += (double)c * S.q[j];
+                cv = (double)c;
                 const int off = j - tbase;
                 wide = wide || off - (TILE - SLICE) < -32768 || off > 32767;
             }
+            acc += cv * qj;
             nbuf += __popc(gm);
             __builtin_amdgcn_wave_barrier();
             if (nbuf >= FL) {
@@ -210,12 +226,14 @@ constexpr int HS_CH = 32;                // entries per row and chunk (4 lanes x
 constexpr int HS_LPR = 4;                // lanes reading one row's chunk
 
 // entries e0 .. e0+7 of a row-major row (fewer when the row ends first)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 template <typename T>
-__device__ __forceinline__ void load8(const T *row, int e0, int cnt, bool vec, T (&out)[8])
+__device__ __forceinline__ void load8(const __attribute__((address_space(1))) T *row, int e0, int cnt, bool vec,
+                                      T (&out)[8])
 {
     if (vec && e0 + 8 <= cnt) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(row + e0);
-        uint4 w[8 * sizeof(T) / 16];
+        const __attribute__((address_space(1))) u32x4 *src = (const __attribute__((address_space(1))) u32x4 *)(row + e0);
+        u32x4 w[8 * sizeof(T) / 16];
 #pragma unroll
         for (int k = 0; k < (int)(8 * sizeof(T) / 16); k++) w[k] = src[k];
         memcpy(out, w, sizeof out);
@@ -269,7 +287,9 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
     const double slots = (tid & (SLICE - 1)) == 0 ? (double)SLICE * (double)slot_cnt[tid] : 0.0;
     __syncthreads();                         // every slice's form (sw) is set
     const R *Hr = reinterpret_cast<const R *>(S.Hr);
-    R *H = reinterpret_cast<R *>(S.H);
+    const auto H = gblw(reinterpret_cast<R *>(S.H));
+    const auto hsidx = gblw(S.hsidx);
+    const auto hs16 = gblw(S.hs16);
     const bool vec = (S.Wl & 3) == 0;        // rows start on 16-byte boundaries
     for (int sl = 0; sl < TILE / SLICE; sl++) {
         const int slot0 = sl * SLICE;
@@ -281,8 +301,8 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
         const int rrk = slot_row[slot0 + rl];
         const int rcnt = slot_cnt[slot0 + rl];
         const int rbb = (T.row0 + rrk) & ~(BK - 1);
-        const uint32_t *irow = S.hidx + (size_t)(T.row0 + rrk) * S.Wl;
-        const R *vrow = Hr + (size_t)(T.row0 + rrk) * S.Wl;
+        const auto irow = gbl(S.hidx + (size_t)(T.row0 + rrk) * S.Wl);
+        const auto vrow = gbl(Hr + (size_t)(T.row0 + rrk) * S.Wl);
         // writing: lane l of wave w takes entries w, w+4, ... of slot l's chunk
         const int wl = tid % SLICE, wq = tid / SLICE;
         const int wcnt = slot_cnt[slot0 + wl];
@@ -315,8 +335,8 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
                 const int e = E0 + c;
                 if (e < wcnt) {
                     const uint32_t ent = ci[wl][c];
-                    if (wide) S.hsidx[b0 + (size_t)e * SLICE] = ent;
-                    else S.hs16[b0 + (size_t)e * SLICE] = (uint16_t)((int)(ent & J_MASK) - sbase + 32768);
+                    if (wide) hsidx[b0 + (size_t)e * SLICE] = ent;
+                    else hs16[b0 + (size_t)e * SLICE] = (uint16_t)((int)(ent & J_MASK) - sbase + 32768);
                     H[b0 + (size_t)e * SLICE] = cv[wl][c];
                 }
             }
@@ -391,9 +411,9 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
 // y = M r for row s: the row of s's block inverse against the block's r,
 // exchanged by shuffles within the BK lanes of the block (every lane of the
 // block must call it; rows past n pass r = 0).
-__device__ __forceinline__ double block_apply(const Seg &S, int s, double r)
+__device__ __forceinline__ double block_apply(const float *binv, int s, double r)
 {
-    const float *B = S.binv + (size_t)(s & ~(BK - 1)) * BK + (s & (BK - 1));
+    const auto B = gbl(binv + (size_t)(s & ~(BK - 1)) * BK + (s & (BK - 1)));
     double y = 0.0;
 #pragma unroll
     for (int t = 0; t < BK; t++) y += (double)B[t * BK] * __shfl(r, t, BK);
@@ -428,16 +448,21 @@ __global__ void __launch_bounds__(TILE) k_shift_stats(const Tile *tiles, Seg *se
     __shared__ double lds[4 * 4];
     const int s = T.row0 + threadIdx.x;
     const bool live = s < S.n;
+    // the segment's pointers in registers before the first store
+    const auto rv = gblw(S.r);
+    const auto yv = gblw(S.y);
+    const auto m1 = gbl(S.m1);
+    const float *binv = S.binv;
     double r = 0.0;
     if (live) {
-        r = S.r[s] - S.sst->w;
-        S.r[s] = r;
+        r = rv[s] - S.sst->w;
+        rv[s] = r;
     }
-    const double y = block_apply(S, s, r);
+    const double y = block_apply(binv, s, r);
     double v[4] = {0, 0, 0, 0};
     if (live) {
-        S.y[s] = y;
-        v[0] = r * S.m1[s];
+        yv[s] = y;
+        v[0] = r * m1[s];
         v[1] = r * y;
         v[2] = r;
         v[3] = r * r;
@@ -477,17 +502,23 @@ __global__ void __launch_bounds__(TILE) k_cg_dir(const Tile *tiles, Seg *segs)
     const int s = T.row0 + threadIdx.x;
     if (s >= S.n) return;
     const double w = S.sst->w, beta = S.sst->beta;
-    const double r = S.r[s] - w;
-    S.r[s] = r;
-    S.p[s] = (S.y[s] - w * S.m1[s]) + beta * S.p[s];
+    const auto rv = gblw(S.r);
+    const auto pv = gblw(S.p);
+    const double y = gbl(S.y)[s], m1 = gbl(S.m1)[s], p = pv[s];
+    const double r = rv[s] - w;
+    rv[s] = r;
+    pv[s] = (y - w * m1) + beta * p;
 }
 
 // s = H p and the tile's share of p^T s, one row per lane; U entries of the
 // row are loaded before their products are summed, so U gathers of p are in
 // flight per lane (U accumulators, combined in a fixed order at the end).
 template <typename R, int U, typename IDX>
-__device__ __forceinline__ double spmv_row(const double *p, const IDX *row, const R *hrow, int cnt, int jbase)
+__device__ __forceinline__ double spmv_row(const double *p_, const IDX *row_, const R *hrow_, int cnt, int jbase)
 {
+    const auto p = gbl(p_);
+    const auto row = gbl(row_);
+    const auto hrow = gbl(hrow_);
     double acc[U];
 #pragma unroll
     for (int u = 0; u < U; u++) acc[u] = 0.0;
@@ -573,18 +604,26 @@ __global__ void __launch_bounds__(TILE) k_cg_update(const Tile *tiles, Seg *segs
     const int s = T.row0 + threadIdx.x;
     const bool live = s < S.n;
     const double alpha = S.sst->alpha;
+    // the segment's pointers in registers before the first store
+    const auto qv = gblw(S.q);
+    const auto rv = gblw(S.r);
+    const auto yv = gblw(S.y);
+    const auto pv = gbl(S.p);
+    const auto sv = gbl(S.s);
+    const auto m1 = gbl(S.m1);
+    const float *binv = S.binv;
     double q = 0.0, r = 0.0;
     if (live) {
-        q = S.q[s] + alpha * S.p[s];
-        r = S.r[s] - alpha * S.s[s];
-        S.q[s] = q;
-        S.r[s] = r;
+        q = qv[s] + alpha * pv[s];
+        r = rv[s] - alpha * sv[s];
+        qv[s] = q;
+        rv[s] = r;
     }
-    const double y = block_apply(S, s, r);
+    const double y = block_apply(binv, s, r);
     double v[5] = {0, 0, 0, 0, 0};
     if (live) {
-        S.y[s] = y;
-        v[0] = r * S.m1[s];
+        yv[s] = y;
+        v[0] = r * m1[s];
         v[1] = r * y;
         v[2] = r;
         v[3] = r * r;
@@ -632,6 +671,7 @@ __global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *seg
     __shared__ double lds[4];
     load_dtab2<R>(S, dtab);
     const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
+    const auto qv = gbl(S.q);
     const double qsh = S.sst->qshift;
     const bool keep_hist = S.q_h1 != nullptr;
     constexpr int G = TILE / LPR;
@@ -642,19 +682,20 @@ __global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *seg
         if (s >= S.n) continue;
         const V4 li = xs[s];
         const int ti = (int)li.w;
+        const double g3_0 = PD.g3[ti * 2], g3_1 = PD.g3[ti * 2 + 1];
         const int cnt = S.hcnt[s];
-        const uint32_t *row = S.hidx + (size_t)s * S.Wl;
+        const auto row = gbl(S.hidx + (size_t)s * S.Wl);
         double ec = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
         for (int e = lane; e < cnt; e += LPR) {
             const uint32_t ent = row[e];
             const int j = (int)(ent & J_MASK);
-            const V4 lj = xs[j];
+            const V4 lj = ld4<R>(xs, j);
+            const double qj = qv[j] + qsh;
             R3<R> d;
             const double r = entry_r<R>(li, lj, dtab[ent >> CODE_SHIFT], d);
             if (r >= PD.rc) continue;          // never taken: the rows hold entries inside rc
             double dCr;
-            const double c = coul64(PD, ti * 2 + (int)lj.w, r, dCr);
-            const double qj = S.q[j] + qsh;
+            const double c = coul64_g(PD, (int)lj.w ? g3_1 : g3_0, r, dCr);
             ec += c * qj;
             if (j != s) {
                 const double g = qj * dCr;

@@ -168,47 +168,53 @@ __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Par
         return;
     }
     const double4 *xs = S.xs64;
-    const double4 li = xs[s];
+    const double4 li = ld4<double>(xs, s);
     const int ti = (int)li.w;
-    const size_t rl = (size_t)s * S.Ws;
+    const int Wb = S.Wb, Ws = S.Ws;
+    const size_t rl = (size_t)s * Ws;
     const int ns = S.scnt[s];
+    const auto sidx = gbl(S.sidx + rl);
+    const auto srev = gbl(S.srev + rl);
+    const auto bidx = gblw(S.bidx + slice_base(s, Wb));
+    const auto bsrev = gblw(S.bsrev + slice_base(s, Wb));
+    const auto cmap = gblw(S.cmap + slice_base(s, Ws));
     int nb = 0;
     for (int e = 0; e < ns; e++) {
-        const uint32_t ent = S.sidx[rl + e];
-        const double4 lj = xs[ent & J_MASK];
+        const uint32_t ent = sidx[e];
+        const double4 lj = ld4<double>(xs, ent & J_MASK);
         const int pp = ti * 2 + (int)lj.w;
         const R3<double> d = pair_vec<double>(li, lj, dtab[ent >> CODE_SHIFT]);
         const double r2 = d.x * d.x + d.y * d.y + d.z * d.z;
         uint8_t c = 255;
         if (r2 < P.Sc[pp] * P.Sc[pp]) {
-            if (nb < S.Wb) {
-                S.bidx[sliced(s, nb, S.Wb)] = ent;
-                S.bsrev[sliced(s, nb, S.Wb)] = S.srev[rl + e];
+            if (nb < Wb) {
+                bidx[(size_t)nb * SLICE] = ent;
+                bsrev[(size_t)nb * SLICE] = srev[e];
                 c = (uint8_t)nb;
             }
             nb++;
         }
-        S.cmap[sliced(s, e, S.Ws)] = c;
+        cmap[(size_t)e * SLICE] = c;
     }
-    if (nb > S.Wb) {
+    if (nb > Wb) {
         atomicOr(&S.sst->status, ST_OVERFLOW);
-        nb = S.Wb;
+        nb = Wb;
     }
     S.bcnt[s] = nb;
-    const SRow<V4> slot = srow(reinterpret_cast<V4 *>(S.slot), s, S.Wb);
-    const SRow<const uint32_t> row = srow<const uint32_t>(S.bidx, s, S.Wb);
+    V4 *slot = reinterpret_cast<V4 *>(S.slot) + slice_base(s, Wb);
+    const auto row = gbl(S.bidx + slice_base(s, Wb));
     double ecov = 0.0;
     for (int e = 0; e < nb; e++) {
-        const uint32_t ent = row[e];
-        const double4 lj = xs[ent & J_MASK];
+        const uint32_t ent = row[(size_t)e * SLICE];
+        const double4 lj = ld4<double>(xs, ent & J_MASK);
         const int pp = ti * 2 + (int)lj.w;
         const R3<double> d = pair_vec<double>(li, lj, dtab[ent >> CODE_SHIFT]);
         const double r = sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
         double z1 = 0, z2 = 0;
         for (int e2 = 0; e2 < nb; e2++) {
             if (e2 == e) continue;
-            const uint32_t ent2 = row[e2];
-            const double4 lk = xs[ent2 & J_MASK];
+            const uint32_t ent2 = row[(size_t)e2 * SLICE];
+            const double4 lk = ld4<double>(xs, ent2 & J_MASK);
             const int pk = ti * 2 + (int)lk.w;
             const R3<double> dk = pair_vec<double>(li, lk, dtab[ent2 >> CODE_SHIFT]);
             const double rk = sqrt(dk.x * dk.x + dk.y * dk.y + dk.z * dk.z);
@@ -233,7 +239,7 @@ __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Par
         out.y = (R)(-0.5 * fc * fA * db1);
         out.z = (R)(-0.5 * fc * fA * db2);
         out.w = (R)0;
-        slot[e] = out;
+        st4<R>(slot, (size_t)e * SLICE, out);
     }
     S.ecov[s] = ecov;
 }
@@ -268,27 +274,31 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
     if (m >= S.n) return;
     const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
     const V4 *slot = reinterpret_cast<const V4 *>(S.slot);
-    const V4 lm = xs[m];
+    const int Wb = S.Wb, Ws = S.Ws;
+    const auto bcnt = gbl(S.bcnt);
+    const auto bsrev = gbl(S.bsrev);
+    const auto cmap = gbl(S.cmap);
+    const V4 lm = ld4<R>(xs, m);
     const int tm = (int)lm.w;
-    const int nb = S.bcnt[m];
-    const SRow<const uint32_t> row = srow<const uint32_t>(S.bidx, m, S.Wb);
-    const SRow<const V4> slm = srow(slot, m, S.Wb);
+    const int nb = bcnt[m];
+    const auto row = gbl(S.bidx + slice_base(m, Wb));
+    const size_t slm = slice_base(m, Wb);
     double fx = 0, fy = 0, fz = 0;
     // m as the centre of its own bonds
     for (int e = 0; e < nb; e++) {
-        const uint32_t ent = row[e];
-        const V4 lj = xs[ent & J_MASK];
+        const uint32_t ent = row[(size_t)e * SLICE];
+        const V4 lj = ld4<R>(xs, ent & J_MASK);
         const int pp = tm * 2 + (int)lj.w;
         const R3<R> d = pair_vec<R>(lm, lj, dtab[ent >> CODE_SHIFT]);
         const R r = dev_sqrt(d.x * d.x + d.y * d.y + d.z * d.z), ir = (R)1 / r;
-        const V4 sv = slm[e];
+        const V4 sv = ld4<R>(slot, slm + (size_t)e * SLICE);
         const R dv = pair_dvdr(P, pp, r, sv.x) * ir;
         R ax = dv * d.x, ay = dv * d.y, az = dv * d.z;
         if (sv.y != (R)0 || sv.z != (R)0) {
             for (int e2 = 0; e2 < nb; e2++) {
                 if (e2 == e) continue;
-                const uint32_t ent2 = row[e2];
-                const V4 lk = xs[ent2 & J_MASK];
+                const uint32_t ent2 = row[(size_t)e2 * SLICE];
+                const V4 lk = ld4<R>(xs, ent2 & J_MASK);
                 const int pk = tm * 2 + (int)lk.w;
                 const R3<R> dk = pair_vec<R>(lm, lk, dtab[ent2 >> CODE_SHIFT]);
                 R3<R> gj[2], gk[2];
@@ -304,25 +314,26 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
     }
     // m as the partner j or the environment k of its neighbours' bonds
     for (int e = 0; e < nb; e++) {
-        const uint32_t ent = row[e];
+        const uint32_t ent = row[(size_t)e * SLICE];
         const int i = (int)(ent & J_MASK);
-        const V4 li = xs[i];
+        const V4 li = ld4<R>(xs, i);
         const int ti = (int)li.w, pp = ti * 2 + tm;
-        const int ni = S.bcnt[i];
-        const int rv = reverse_bond(S, m, e, i);              // bond (i -> m) in row i
+        const int ni = bcnt[i];
+        // bond (i -> m) in row i
+        const int rv = cmap[slice_base(i, Ws) + (size_t)bsrev[slm + (size_t)e * SLICE] * SLICE];
         if (rv >= ni) continue;                               // (a reverse always exists)
         const R3<R> dmi = pair_vec<R>(lm, li, dtab[ent >> CODE_SHIFT]);
         const R r = dev_sqrt(dmi.x * dmi.x + dmi.y * dmi.y + dmi.z * dmi.z), ir = (R)1 / r;
         const R3<R> d = {-dmi.x, -dmi.y, -dmi.z};            // i -> m
-        const SRow<const V4> sli = srow(slot, i, S.Wb);
-        const V4 sv = sli[rv];
+        const size_t sli = slice_base(i, Wb);
+        const V4 sv = ld4<R>(slot, sli + (size_t)rv * SLICE);
         const R dv = pair_dvdr(P, pp, r, sv.x) * ir;
         R ax = -dv * d.x, ay = -dv * d.y, az = -dv * d.z;
-        const SRow<const uint32_t> rowi = srow<const uint32_t>(S.bidx, i, S.Wb);
+        const auto rowi = gbl(S.bidx + sli);
         for (int t = 0; t < ni; t++) {
             if (t == rv) continue;
-            const uint32_t ent2 = rowi[t];
-            const V4 lk = xs[ent2 & J_MASK];
+            const uint32_t ent2 = rowi[(size_t)t * SLICE];
+            const V4 lk = ld4<R>(xs, ent2 & J_MASK);
             const int pk = ti * 2 + (int)lk.w;
             const R3<R> dk = pair_vec<R>(li, lk, dtab[ent2 >> CODE_SHIFT]);   // i -> k
             const R rk = dev_sqrt(dk.x * dk.x + dk.y * dk.y + dk.z * dk.z);
@@ -334,7 +345,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
                 ay -= sv.y * gj[0].y + sv.z * gj[1].y;
                 az -= sv.y * gj[0].z + sv.z * gj[1].z;
             }
-            const V4 sk = sli[t];                               // bond (i -> k)
+            const V4 sk = ld4<R>(slot, sli + (size_t)t * SLICE);   // bond (i -> k)
             if (sk.y != (R)0 || sk.z != (R)0) {
                 // bond (i -> k), environment m: m is the environment atom
                 trip_grad(P, ti, pp, dk, rk, d, r, gj, gk);
