@@ -293,6 +293,7 @@ __global__ void __launch_bounds__(TILE) k_build(const Tile *tiles, Seg *segs, Pa
         if (s >= n) continue;                  // the whole group skips together
         const V4 li = ld4<R>(xs, s);
         const int ti = (int)li.w;
+        const float sc2_0 = P.s_cut2[ti * 2], sc2_1 = P.s_cut2[ti * 2 + 1];
         const int c = csort[s];
         const int c0 = c / (nb1 * nb2), c1 = (c / nb2) % nb1, c2 = c % nb2;
         const auto lrow = gblw(S.lidx + (size_t)s * Wl);
@@ -337,7 +338,7 @@ __global__ void __launch_bounds__(TILE) k_build(const Tile *tiles, Seg *segs, Pa
                             if (r2 < P.l_cut2) {
                                 inl = true;
                                 if (r2 < P.close2) close = true;
-                                ins = r2 < P.s_cut2[ti * 2 + (int)lj.w];
+                                ins = r2 < ((int)lj.w ? sc2_1 : sc2_0);
                                 ent = (uint32_t)m | ((uint32_t)code << CODE_SHIFT);
                             }
                         }

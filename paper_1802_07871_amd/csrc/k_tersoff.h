@@ -142,6 +142,18 @@ __device__ __forceinline__ void load_dtab2(const Seg &S, typename Vec4<R>::type 
     __syncthreads();
 }
 
+// The parameters in LDS: the triplet loops index them by species, and
+// per-lane indexed reads of the kernel-argument copy go through the vector
+// memory path (and are read again in every iteration for want of registers).
+template <typename P>
+__device__ __forceinline__ void stage_params(const P &src, P &dst)
+{
+    static_assert(sizeof(P) % 4 == 0, "parameter block of whole words");
+    const int *a = reinterpret_cast<const int *>(&src);
+    int *b = reinterpret_cast<int *>(&dst);
+    for (int k = threadIdx.x; k < (int)(sizeof(P) / 4); k += blockDim.x) b[k] = a[k];
+}
+
 // Bond pass.  First the bonds of the step: the covalent-list entries inside
 // S_ij, by the FP64 distance used below, compacted in list order (so every
 // loop over bonds and triplets runs over bonds only; the skin shell of the
@@ -152,13 +164,16 @@ __device__ __forceinline__ void load_dtab2(const Seg &S, typename Vec4<R>::type 
 // FP32 rounding in zeta, b and the large, cancelling fR and b fA terms.  The
 // coefficients are stored in the pair precision R for the force gather.
 template <typename R>
-__global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Params<double> P)
+__global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Params<double> Pk)
 {
     using V4 = typename Vec4<R>::type;
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     __shared__ double4 dtab[NCODE];
-    load_dtab2<double>(S, dtab);
+    __shared__ Params<double> Pl;
+    stage_params(Pk, Pl);
+    load_dtab2<double>(S, dtab);            // (ends with a barrier)
+    const Params<double> &P = Pl;
     const int s = T.row0 + threadIdx.x;
     if (s >= S.n) {
         if (s < S.npad) {
@@ -261,7 +276,7 @@ __device__ __forceinline__ R pair_dvdr(const Params<R> &P, int pp, R r, R b)
 }
 
 template <typename R>
-__global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs, Params<R> P, int gate)
+__global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs, Params<R> Pk, int gate)
 {
     using V4 = typename Vec4<R>::type;
     const Tile T = my_tile(tiles);
@@ -269,7 +284,10 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
     // serving: only segments whose charge solve finished and whose forces are pending
     if (gate && (!S.sst->done || S.sst->forces_done)) return;
     __shared__ V4 dtab[NCODE];
-    load_dtab2<R>(S, dtab);
+    __shared__ Params<R> Pl;
+    stage_params(Pk, Pl);
+    load_dtab2<R>(S, dtab);                 // (ends with a barrier)
+    const Params<R> &P = Pl;
     const int m = T.row0 + threadIdx.x;
     if (m >= S.n) return;
     const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
