@@ -205,3 +205,22 @@ def test_caller_stream_orders_results(ct, theta):
             runs.append((x.clone(), th.copy()))
         side.synchronize()
     assert bool((runs[0][0] == runs[1][0]).all()) and np.array_equal(runs[0][1], runs[1][1])
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_row_width_does_not_change_results(ct, theta, fp64):
+    """The Coulomb rows are stored with the list width as their stride; the
+    sliced copy reads them in 16-byte vectors when the width is a multiple of
+    four and entry by entry otherwise. Widths 512, 509 and 401 (all above the
+    longest row) must give the same energy, forces and charges bit for bit."""
+    s = CASES["stepped slab"]
+    out = []
+    for cap in (512, 509, 401):
+        print(f"[row width] long_cap={cap} fp64={fp64}", flush=True)
+        E, F, q, info = ct.Potential(theta, long_cap=cap, fp64=fp64).compute(s.pos, s.types, s.box, s.pbc,
+                                                                             warm=False)
+        assert info["status"] == 0
+        out.append((E, F.cpu().numpy(), q.cpu().numpy()))
+    for E, F, q in out[1:]:
+        assert E == out[0][0]
+        assert np.array_equal(F, out[0][1]) and np.array_equal(q, out[0][2])
