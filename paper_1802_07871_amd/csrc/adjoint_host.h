@@ -38,6 +38,7 @@ void fill_params_dual(const double *theta, int k, const ctbop_opts &o, Params<Du
             P.gam[a][l] = ch[0];
             P.c2[a][l] = ch[1] * ch[1];
             P.d2[a][l] = ch[2] * ch[2];
+            P.c2d2[a][l] = (ch[1] / ch[2]) * (ch[1] / ch[2]);
             P.h[a][l] = ch[3];
             P.nn[a][l] = ch[4];
             P.g[a][l] = ch[5];

@@ -124,6 +124,7 @@ void fill_params(const double *t, const ctbop_opts &o, Params<R> &P)
             P.gam[a][l] = (R)ch[0];
             P.c2[a][l] = (R)(ch[1] * ch[1]);
             P.d2[a][l] = (R)(ch[2] * ch[2]);
+            P.c2d2[a][l] = (R)((ch[1] / ch[2]) * (ch[1] / ch[2]));
             P.h[a][l] = (R)ch[3];
             P.nn[a][l] = (R)ch[4];
             P.g[a][l] = (R)ch[5];

@@ -38,6 +38,7 @@ struct Params {
     // centre species: normalisation G, 1/(2 sigma), channel constants
     R G[2], inv2sig[2];
     R gam[2][2], c2[2][2], d2[2][2], h[2][2], nn[2][2], g[2][2], alpha[2][2];
+    R c2d2[2][2];                      // c^2 / d^2 of the angular function
     R p;
     int p_is_2;
     int alpha_zero[2];                 // both channels of species t have alpha == 0

@@ -39,14 +39,15 @@ __device__ __forceinline__ R cutoff(R r, R Rc, R Sc, R piSR, R &dfc)
     return (R)0.5 + (R)0.5 * cs;
 }
 
-// angular function of channel l for centre species t (and d/dcos)
+// angular function of channel l for centre species t (and d/dcos):
+// w = gam (1 + (c^2/d^2) x^2 / (d^2 + x^2)), x = h - cos, one division
 template <typename R>
 __device__ __forceinline__ R angular(const Params<R> &P, int t, int l, R cs, R &dw)
 {
-    R x = P.h[t][l] - cs;
-    R den = P.d2[t][l] + x * x;
-    R w = P.gam[t][l] * ((R)1 + P.c2[t][l] * x * x / (P.d2[t][l] * den));
-    dw = -P.gam[t][l] * P.c2[t][l] * (R)2 * x / (den * den);
+    const R x = P.h[t][l] - cs;
+    const R iden = (R)1 / (P.d2[t][l] + x * x);
+    const R w = P.gam[t][l] * ((R)1 + P.c2d2[t][l] * x * x * iden);
+    dw = -P.gam[t][l] * P.c2[t][l] * (R)2 * x * iden * iden;
     return w;
 }
 
