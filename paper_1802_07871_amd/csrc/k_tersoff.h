@@ -143,6 +143,8 @@ __device__ __forceinline__ void load_dtab2(const Seg &S, typename Vec4<R>::type 
     __syncthreads();
 }
 
+constexpr int BOND_CACHE = 4;           // bonds per atom whose geometry the bond pass keeps in LDS
+
 // The parameters in LDS: the triplet loops index them by species, and
 // per-lane indexed reads of the kernel-argument copy go through the vector
 // memory path (and are read again in every iteration for want of registers).
@@ -172,6 +174,11 @@ __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Par
     const Seg &S = segs[T.seg];
     __shared__ double4 dtab[NCODE];
     __shared__ Params<double> Pl;
+    // the first BOND_CACHE bonds of each thread's atom: vector, length,
+    // cutoff value and pair type, computed once for the triplet loop
+    __shared__ double cbx[BOND_CACHE][TILE], cby[BOND_CACHE][TILE], cbz[BOND_CACHE][TILE];
+    __shared__ double cbr[BOND_CACHE][TILE], cbf[BOND_CACHE][TILE];
+    __shared__ uint8_t cbp[BOND_CACHE][TILE];
     stage_params(Pk, Pl);
     load_dtab2<double>(S, dtab);            // (ends with a barrier)
     const Params<double> &P = Pl;
@@ -219,24 +226,55 @@ __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Par
     S.bcnt[s] = nb;
     V4 *slot = reinterpret_cast<V4 *>(S.slot) + slice_base(s, Wb);
     const auto row = gbl(S.bidx + slice_base(s, Wb));
-    double ecov = 0.0;
-    for (int e = 0; e < nb; e++) {
+    // bond e of the atom: vector, length, cutoff value, pair type
+    auto bond_geom = [&](int e, R3<double> &d, double &r, double &fcut, int &pp) {
         const uint32_t ent = row[(size_t)e * SLICE];
         const double4 lj = ld4<double>(xs, ent & J_MASK);
-        const int pp = ti * 2 + (int)lj.w;
-        const R3<double> d = pair_vec<double>(li, lj, dtab[ent >> CODE_SHIFT]);
-        const double r = sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
+        pp = ti * 2 + (int)lj.w;
+        d = pair_vec<double>(li, lj, dtab[ent >> CODE_SHIFT]);
+        r = sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
+        double dummy;
+        fcut = cutoff<double>(r, P.Rc[pp], P.Sc[pp], P.piSR[pp], dummy);
+    };
+    auto bond = [&](int e, R3<double> &d, double &r, double &fcut, int &pp) {
+        if (e < BOND_CACHE) {
+            d.x = cbx[e][threadIdx.x];
+            d.y = cby[e][threadIdx.x];
+            d.z = cbz[e][threadIdx.x];
+            r = cbr[e][threadIdx.x];
+            fcut = cbf[e][threadIdx.x];
+            pp = cbp[e][threadIdx.x];
+        } else {
+            bond_geom(e, d, r, fcut, pp);
+        }
+    };
+    for (int e = 0; e < min(nb, BOND_CACHE); e++) {
+        R3<double> d;
+        double r, fcut;
+        int pp;
+        bond_geom(e, d, r, fcut, pp);
+        cbx[e][threadIdx.x] = d.x;
+        cby[e][threadIdx.x] = d.y;
+        cbz[e][threadIdx.x] = d.z;
+        cbr[e][threadIdx.x] = r;
+        cbf[e][threadIdx.x] = fcut;
+        cbp[e][threadIdx.x] = (uint8_t)pp;
+    }
+    double ecov = 0.0;
+    for (int e = 0; e < nb; e++) {
+        R3<double> d;
+        double r, fc;
+        int pp;
+        bond(e, d, r, fc, pp);
         double z1 = 0, z2 = 0;
         for (int e2 = 0; e2 < nb; e2++) {
             if (e2 == e) continue;
-            const uint32_t ent2 = row[(size_t)e2 * SLICE];
-            const double4 lk = ld4<double>(xs, ent2 & J_MASK);
-            const int pk = ti * 2 + (int)lk.w;
-            const R3<double> dk = pair_vec<double>(li, lk, dtab[ent2 >> CODE_SHIFT]);
-            const double rk = sqrt(dk.x * dk.x + dk.y * dk.y + dk.z * dk.z);
+            R3<double> dk;
+            double rk, fk;
+            int pk;
+            bond(e2, dk, rk, fk, pk);
             const double cs = (d.x * dk.x + d.y * dk.y + d.z * dk.z) / (r * rk);
-            double dummy, dw, dex;
-            const double fk = cutoff<double>(rk, P.Rc[pk], P.Sc[pk], P.piSR[pk], dummy);
+            double dw, dex;
             double w1 = angular<double>(P, ti, 0, cs, dw), w2 = angular<double>(P, ti, 1, cs, dw);
             if (!P.alpha_zero[ti]) {
                 w1 *= radial<double>(P, ti, 0, r - rk, dex);
@@ -245,9 +283,8 @@ __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Par
             z1 += fk * w1;
             z2 += fk * w2;
         }
-        double db1, db2, dfc;
+        double db1, db2;
         const double b = bond_order<double>(P, ti, z1, z2, db1, db2);
-        const double fc = cutoff<double>(r, P.Rc[pp], P.Sc[pp], P.piSR[pp], dfc);
         const double fR = P.A[pp] * exp(-P.lam1[pp] * r), fA = P.B[pp] * exp(-P.lam2[pp] * r);
         ecov += 0.5 * fc * (fR - b * fA);
         V4 out;
