@@ -693,9 +693,14 @@ __global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *seg
             const double qj = qv[j] + qsh;
             R3<R> d;
             const double r = entry_r<R>(li, lj, dtab[ent >> CODE_SHIFT], d);
-            if (r >= PD.rc) continue;          // never taken: the rows hold entries inside rc
+            // every entry lies inside rc (the rows were selected by this same
+            // distance); a select rather than a branch keeps the loop body in
+            // one block, so the charge load issues beside the position load
+            const bool in = r < PD.rc;
             double dCr;
-            const double c = coul64_g(PD, (int)lj.w ? g3_1 : g3_0, r, dCr);
+            double c = coul64_g(PD, (int)lj.w ? g3_1 : g3_0, r, dCr);
+            c = in ? c : 0.0;
+            dCr = in ? dCr : 0.0;
             ec += c * qj;
             if (j != s) {
                 const double g = qj * dCr;
