@@ -313,6 +313,11 @@ int ctbop_status(ctbop_ctx *ctx, void *sys_dev, size_t sys_bytes, void *stream, 
  * 11 chain bonds. */
 int ctbop_profile(ctbop_ctx *ctx, int enable, int reset, void *stream, double *ms_out, long *count_out, int nk);
 
+/* Kernel classes that ctbop_profile times while it is on: bit k for class k
+ * (default: all). Events cost the work they bracket a little, so a
+ * measurement of one kernel can time that class alone. */
+int ctbop_profile_classes(ctbop_ctx *ctx, unsigned mask);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *ctbop_last_error(void);
 

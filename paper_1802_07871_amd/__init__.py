@@ -55,7 +55,7 @@ class Info(ctypes.Structure):
 _lib = None
 EXPORTS = ("ctbop_default_opts", "ctbop_create", "ctbop_destroy", "ctbop_system_bytes",
            "ctbop_compute_energy_forces_charges", "ctbop_md_run", "ctbop_status", "ctbop_last_error",
-           "ctbop_debug_lists", "ctbop_profile", "ctbop_set_params", "ctbop_param_grad_bytes", "ctbop_param_grad",
+           "ctbop_debug_lists", "ctbop_profile", "ctbop_profile_classes", "ctbop_set_params", "ctbop_param_grad_bytes", "ctbop_param_grad",
            "ctbop_removal_bytes", "ctbop_removal_energies", "ctbop_md_run_nvt", "ctbop_relax_fire",
            "ctbop_rings_bytes", "ctbop_rings")
 
@@ -80,6 +80,7 @@ def lib():
         L.ctbop_last_error.restype = ctypes.c_char_p
         L.ctbop_debug_lists.argtypes = [vp, i32, vp, sz, i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.ctbop_profile.argtypes = [vp, i32, i32, vp, vp, vp, i32]
+        L.ctbop_profile_classes.argtypes = [vp, ctypes.c_uint]
         L.ctbop_set_params.argtypes = [vp, vp, i32]
         L.ctbop_param_grad_bytes.argtypes = [vp, i32, vp, vp, ctypes.POINTER(sz)]
         L.ctbop_param_grad.argtypes = [vp, i32, vp, vp, vp, sz, vp, sz, dbl, vp, vp, vp, ctypes.POINTER(i32), vp]
@@ -407,9 +408,12 @@ class Potential:
     KERNELS = ("spmv", "force_coul", "assemble", "bond", "force_cov", "cg_update", "cg_dir", "build", "hslice",
                "ring_adj", "rings", "ring_chain")
 
-    def profile(self, enable=True, reset=True):
+    def profile(self, enable=True, reset=True, classes=None):
         """Per-kernel event timing: returns {name: (ms_total, launches)} accumulated
-        so far, then sets timing on/off (and clears the totals if reset)."""
+        so far, then sets timing on/off (and clears the totals if reset). classes:
+        names from KERNELS to time from now on (None: all)."""
+        mask = 0xFFFF if classes is None else sum(1 << self.KERNELS.index(k) for k in classes)
+        _check(lib().ctbop_profile_classes(self.ctx, mask))
         ms = np.zeros(16)
         cnt = np.zeros(16, dtype=np.int64)
         _check(lib().ctbop_profile(self.ctx, int(enable), int(reset), _stream(), ms.ctypes.data,

@@ -85,6 +85,7 @@ struct ctbop_ctx {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // optional per-kernel timing with HIP events on the caller's stream
     int profile = 0;
+    unsigned profile_mask = 0xffffu;   // kernel classes timed while profiling is on
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
     double prof_ms[16] = {0};
@@ -300,8 +301,11 @@ __global__ void k_reset_state(SegState *st, Tile *tiles, int ntile, int *segid)
 hipEvent_t ev_get(ctbop_ctx *ctx)
 {
     if (ctx->ev_free.empty()) {
+        // timing only: no system-scope fence (cache writeback and invalidate)
+        // when the event is recorded, which would slow the work it brackets;
+        // the stream is synchronised before any time is read
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
         return e;
     }
     hipEvent_t e = ctx->ev_free.back();
@@ -318,7 +322,7 @@ struct Timed {
     hipEvent_t a = nullptr;
     Timed(ctbop_ctx *c, int kk, hipStream_t s) : ctx(c), k(kk), st(s)
     {
-        if (ctx->profile) {
+        if (ctx->profile && ((ctx->profile_mask >> k) & 1u)) {
             a = ev_get(ctx);
             if (a) (void)hipEventRecord(a, st);
         }
@@ -986,6 +990,13 @@ int ctbop_profile(ctbop_ctx *ctx, int enable, int reset, void *stream, double *m
             ctx->prof_n[k] = 0;
         }
     ctx->profile = enable ? 1 : 0;
+    return CTBOP_OK;
+}
+
+int ctbop_profile_classes(ctbop_ctx *ctx, unsigned mask)
+{
+    if (!ctx) return fail(CTBOP_E_INVAL, "null context");
+    ctx->profile_mask = mask & 0xffffu;
     return CTBOP_OK;
 }
 
