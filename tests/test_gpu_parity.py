@@ -224,3 +224,21 @@ def test_row_width_does_not_change_results(ct, theta, fp64):
     for E, F, q in out[1:]:
         assert E == out[0][0]
         assert np.array_equal(F, out[0][1]) and np.array_equal(q, out[0][2])
+
+
+def test_profile_classes_select_the_timed_kernels(ct, theta):
+    """ctbop_profile_classes: with one class selected only that kernel is
+    timed; with none given every class is timed again."""
+    s = CASES["stepped slab"]
+    print("[profile classes] stepped slab", flush=True)
+    pot = ct.Potential(theta)
+    pot.profile(enable=True, reset=True, classes=("spmv",))
+    pot.compute(s.pos, s.types, s.box, s.pbc, warm=False)
+    prof = pot.profile(enable=False, reset=True)
+    assert prof["spmv"][1] > 0
+    assert all(c == 0 for k, (ms, c) in prof.items() if k != "spmv")
+    pot.profile(enable=True, reset=True)
+    pot.compute(s.pos, s.types, s.box, s.pbc, warm=False)
+    prof = pot.profile(enable=False, reset=True)
+    for k in ("spmv", "force_coul", "assemble", "bond", "force_cov", "hslice"):
+        assert prof[k][1] > 0 and prof[k][0] > 0.0
