@@ -323,6 +323,9 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
     if (gate && (!S.sst->done || S.sst->forces_done)) return;
     __shared__ V4 dtab[NCODE];
     __shared__ Params<R> Pl;
+    // the first BOND_CACHE bonds of each thread's atom: vector, length, pair type
+    __shared__ R cbx[BOND_CACHE][TILE], cby[BOND_CACHE][TILE], cbz[BOND_CACHE][TILE], cbr[BOND_CACHE][TILE];
+    __shared__ uint8_t cbp[BOND_CACHE][TILE];
     stage_params(Pk, Pl);
     load_dtab2<R>(S, dtab);                 // (ends with a barrier)
     const Params<R> &P = Pl;
@@ -340,25 +343,55 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
     const auto row = gbl(S.bidx + slice_base(m, Wb));
     const size_t slm = slice_base(m, Wb);
     double fx = 0, fy = 0, fz = 0;
-    // m as the centre of its own bonds
-    for (int e = 0; e < nb; e++) {
+    // bond e of m: vector, length, pair type (the first BOND_CACHE from LDS)
+    auto bond_geom = [&](int e, R3<R> &d, R &r, int &pp) {
         const uint32_t ent = row[(size_t)e * SLICE];
         const V4 lj = ld4<R>(xs, ent & J_MASK);
-        const int pp = tm * 2 + (int)lj.w;
-        const R3<R> d = pair_vec<R>(lm, lj, dtab[ent >> CODE_SHIFT]);
-        const R r = dev_sqrt(d.x * d.x + d.y * d.y + d.z * d.z), ir = (R)1 / r;
+        pp = tm * 2 + (int)lj.w;
+        d = pair_vec<R>(lm, lj, dtab[ent >> CODE_SHIFT]);
+        r = dev_sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
+    };
+    auto bond = [&](int e, R3<R> &d, R &r, int &pp) {
+        if (e < BOND_CACHE) {
+            d.x = cbx[e][threadIdx.x];
+            d.y = cby[e][threadIdx.x];
+            d.z = cbz[e][threadIdx.x];
+            r = cbr[e][threadIdx.x];
+            pp = cbp[e][threadIdx.x];
+        } else {
+            bond_geom(e, d, r, pp);
+        }
+    };
+    for (int e = 0; e < min(nb, BOND_CACHE); e++) {
+        R3<R> d;
+        R r;
+        int pp;
+        bond_geom(e, d, r, pp);
+        cbx[e][threadIdx.x] = d.x;
+        cby[e][threadIdx.x] = d.y;
+        cbz[e][threadIdx.x] = d.z;
+        cbr[e][threadIdx.x] = r;
+        cbp[e][threadIdx.x] = (uint8_t)pp;
+    }
+    // m as the centre of its own bonds
+    for (int e = 0; e < nb; e++) {
+        R3<R> d;
+        R r;
+        int pp;
+        bond(e, d, r, pp);
+        const R ir = (R)1 / r;
         const V4 sv = ld4<R>(slot, slm + (size_t)e * SLICE);
         const R dv = pair_dvdr(P, pp, r, sv.x) * ir;
         R ax = dv * d.x, ay = dv * d.y, az = dv * d.z;
         if (sv.y != (R)0 || sv.z != (R)0) {
             for (int e2 = 0; e2 < nb; e2++) {
                 if (e2 == e) continue;
-                const uint32_t ent2 = row[(size_t)e2 * SLICE];
-                const V4 lk = ld4<R>(xs, ent2 & J_MASK);
-                const int pk = tm * 2 + (int)lk.w;
-                const R3<R> dk = pair_vec<R>(lm, lk, dtab[ent2 >> CODE_SHIFT]);
+                R3<R> dk;
+                R rk;
+                int pk;
+                bond(e2, dk, rk, pk);
                 R3<R> gj[2], gk[2];
-                trip_grad(P, tm, pk, d, r, dk, dev_sqrt(dk.x * dk.x + dk.y * dk.y + dk.z * dk.z), gj, gk);
+                trip_grad(P, tm, pk, d, r, dk, rk, gj, gk);
                 ax += sv.y * (gj[0].x + gk[0].x) + sv.z * (gj[1].x + gk[1].x);
                 ay += sv.y * (gj[0].y + gk[0].y) + sv.z * (gj[1].y + gk[1].y);
                 az += sv.z * (gj[1].z + gk[1].z) + sv.y * (gj[0].z + gk[0].z);
