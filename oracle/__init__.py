@@ -111,13 +111,19 @@ def evaluate(pos, types, box, pbc, params, Q=0.0, tol=1e-12, maxit=5000, method=
     return float(E[0]), F, q, d
 
 
-def evaluate_fixed_q(pos, types, box, pbc, params, q, method=-1):
+def evaluate_fixed_q(pos, types, box, pbc, params, q, method=-1, per_atom=False):
+    """Energy and forces at given charges; with per_atom, also the per-atom
+    energy shares (returned as a third value)."""
     pos, types, box, pbc = _geom(pos, types, box, pbc)
     n = len(types)
     E = np.zeros(1)
     F = np.zeros((n, 3))
+    eat = np.zeros(n)
     lib().oracle_eval_fixed_q(n, pos, types, box, pbc, np.ascontiguousarray(params, dtype=np.float64),
-                              np.ascontiguousarray(q, dtype=np.float64), int(method), E, F, None)
+                              np.ascontiguousarray(q, dtype=np.float64), int(method), E, F,
+                              eat.ctypes.data if per_atom else None)
+    if per_atom:
+        return float(E[0]), F, eat
     return float(E[0]), F
 
 
