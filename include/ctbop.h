@@ -153,12 +153,23 @@ int ctbop_set_params(ctbop_ctx *ctx, const double *params_host, int n_params);
  * order and the charges for the warm start); its content is opaque. */
 int ctbop_system_bytes(ctbop_ctx *ctx, int n, const double *box_host, const int *pbc_host, size_t *bytes);
 
+/* Forget what this context knows of the buffer at `sys`: its next use is
+ * set up from scratch (state cleared, lists rebuilt, cold charge start), as
+ * for a buffer never seen.  A context recognises a system buffer by its
+ * address and geometry; call this whenever the memory at `sys` may have held
+ * anything else since this context last used it (for instance a freed
+ * buffer whose address the allocator handed out again).  Host-side only,
+ * no device work. */
+int ctbop_system_reset(ctbop_ctx *ctx, void *sys_dev);
+
 /* Energy, forces and charges (the hot path).
  *   pos_dev   double[3n] SoA positions (any periodic image)
  *   types_dev int32[n]
  *   E_dev     double[1] out; F_dev double[3n] SoA out; q_dev double[n] out
  *   sys_dev   caller buffer of at least ctbop_system_bytes() bytes; pass the
- *             same buffer for successive calls on one system
+ *             same buffer for successive calls on one system (positions and
+ *             species may change between calls: lists are rebuilt once an
+ *             atom moved skin/2 or changed species)
  *   info      host pointer or NULL (NULL: no final wait or report)       */
 int ctbop_compute_energy_forces_charges(ctbop_ctx *ctx, int n, const double *pos_dev,
                                         const int32_t *types_dev, const double *box_host,

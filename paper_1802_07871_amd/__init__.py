@@ -57,7 +57,7 @@ EXPORTS = ("ctbop_default_opts", "ctbop_create", "ctbop_destroy", "ctbop_system_
            "ctbop_compute_energy_forces_charges", "ctbop_md_run", "ctbop_status", "ctbop_last_error",
            "ctbop_debug_lists", "ctbop_profile", "ctbop_profile_classes", "ctbop_set_params", "ctbop_param_grad_bytes", "ctbop_param_grad",
            "ctbop_removal_bytes", "ctbop_removal_energies", "ctbop_md_run_nvt", "ctbop_relax_fire",
-           "ctbop_rings_bytes", "ctbop_rings")
+           "ctbop_rings_bytes", "ctbop_rings", "ctbop_system_reset")
 
 
 def lib():
@@ -72,6 +72,7 @@ def lib():
         L.ctbop_create.argtypes = [vp, i32, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
         L.ctbop_destroy.argtypes = [vp]
         L.ctbop_system_bytes.argtypes = [vp, i32, vp, vp, ctypes.POINTER(sz)]
+        L.ctbop_system_reset.argtypes = [vp, vp]
         L.ctbop_compute_energy_forces_charges.argtypes = [vp, i32, vp, vp, vp, vp, dbl, i32, vp, sz, vp, vp,
                                                           vp, ctypes.POINTER(Info), vp]
         L.ctbop_md_run.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, dbl, dbl, i32, i32, vp, sz, vp, vp, vp,
@@ -132,6 +133,9 @@ class System:
         self.nbytes = int(nbytes.value)
         self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device="cuda")
         self.n = int(n)
+        # the allocator may hand out the address of a freed buffer again: the
+        # context must not take this memory's contents for a system it knows
+        _check(lib().ctbop_system_reset(pot.ctx, self.ptr()))
 
     def ptr(self):
         return ctypes.c_void_p(self.buf.data_ptr())

@@ -689,6 +689,15 @@ int ctbop_system_bytes(ctbop_ctx *ctx, int n, const double *box, const int *pbc,
     return CTBOP_OK;
 }
 
+int ctbop_system_reset(ctbop_ctx *ctx, void *sys)
+{
+    if (!ctx || !sys) return fail(CTBOP_E_INVAL, "null argument");
+    ctx->seen.erase(sys);
+    ctx->last_iters.erase(sys);
+    ctx->eval_gen.erase(sys);
+    return CTBOP_OK;
+}
+
 int ctbop_compute_energy_forces_charges(ctbop_ctx *ctx, int n, const double *pos, const int32_t *types,
                                         const double *box, const int *pbc, double Q, int flags, void *sys,
                                         size_t sys_bytes, double *E, double *F, double *q, ctbop_info *info,

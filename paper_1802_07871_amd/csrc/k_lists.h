@@ -33,7 +33,9 @@ __global__ void k_call_init(const int *seg_ids, Seg *segs, int nseg, int force_r
 }
 
 // A neighbour list rebuild is needed once any atom moved more than skin/2
-// since the last build (then no pair can have crossed into the cutoff).
+// since the last build (then no pair can have crossed into the cutoff), or
+// once any atom changed species: the covalent list's radius is per species
+// pair.  Sorted row i still holds the species of the last gather in xs64.w.
 __global__ void k_check_disp(const Tile *tiles, Seg *segs)
 {
     const Tile T = my_tile(tiles);
@@ -45,7 +47,9 @@ __global__ void k_check_disp(const Tile *tiles, Seg *segs)
     double dy = S.x[S.n + i] - S.ref_x[S.n + i];
     double dz = S.x[2 * S.n + i] - S.ref_x[2 * S.n + i];
     double lim = 0.5 * S.skin;
-    if (dx * dx + dy * dy + dz * dz > lim * lim) S.sst->rebuild = 1;
+    bool moved = dx * dx + dy * dy + dz * dz > lim * lim;
+    bool retyped = (int)S.xs64[i].w != S.type[S.perm[i]];
+    if (moved || retyped) S.sst->rebuild = 1;
 }
 
 // fractional coordinates, folded along periodic vectors; the integer fold is

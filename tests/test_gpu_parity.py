@@ -136,6 +136,52 @@ def test_warm_start_and_determinism(ct, orc, theta):
     assert np.linalg.norm(F5.cpu().numpy() - Fo) / np.linalg.norm(Fo) < 1e-5
 
 
+def test_species_change_rebuilds_lists(ct, orc, theta):
+    """The covalent list's radius depends on the species pair, so a change of
+    species at fixed positions must rebuild the lists (a list built for Si-C
+    pairs would miss Si-Si bonds between 2.51 and 3.0 A)."""
+    s = G.random_system(600, 0.5, 2.4, True, seed=91)
+    print("[species change] periodic 600", flush=True)
+    pot = ct.Potential(theta)
+    sysbuf = pot.system(s.n, s.box, s.pbc)
+    _, _, _, i1 = pot.compute(s.pos, s.types, s.box, s.pbc, warm=False, sysbuf=sysbuf)
+    assert i1["rebuilt"] == 1
+    types = s.types.copy()
+    rng = np.random.Generator(np.random.PCG64(92))
+    flip = rng.choice(s.n, size=s.n // 3, replace=False)
+    types[flip] = 1 - types[flip]
+    E, F, q, i2 = pot.compute(s.pos, types, s.box, s.pbc, warm=True, sysbuf=sysbuf)
+    assert i2["rebuilt"] == 1 and i2["status"] == 0
+    Eo, Fo, qo, _ = orc.evaluate(s.pos, types, s.box, s.pbc, theta, tol=1e-13)
+    t = TOL["mixed"]
+    assert abs(E - Eo) / s.n <= t["E"]
+    assert np.linalg.norm(F.cpu().numpy() - Fo) / np.linalg.norm(Fo) <= t["F"]
+    assert np.abs(q.cpu().numpy() - qo).max() <= t["q"]
+    # unchanged species and positions: no rebuild
+    _, _, _, i3 = pot.compute(s.pos, types, s.box, s.pbc, warm=True, sysbuf=sysbuf)
+    assert i3["rebuilt"] == 0
+
+
+def test_system_reset_starts_over(ct, theta):
+    """After ctbop_system_reset the next call on the same memory is set up
+    from scratch, exactly as a new buffer: the rebuild counter restarts and
+    the results equal a new buffer's cold-start results bit for bit."""
+    import ctypes
+    s = CASES["periodic 1000"]
+    print("[system reset] periodic 1000", flush=True)
+    pot = ct.Potential(theta)
+    sysbuf = pot.system(s.n, s.box, s.pbc)
+    rng = np.random.Generator(np.random.PCG64(93))
+    pos0 = s.pos + rng.normal(0, 0.02, s.pos.shape)
+    pot.compute(pos0, s.types, s.box, s.pbc, warm=False, sysbuf=sysbuf)
+    pot.compute(s.pos, s.types, s.box, s.pbc, warm=True, sysbuf=sysbuf)
+    assert ct.lib().ctbop_system_reset(pot.ctx, ctypes.c_void_p(sysbuf.buf.data_ptr())) == 0
+    E1, F1, q1, i1 = pot.compute(s.pos, s.types, s.box, s.pbc, warm=True, sysbuf=sysbuf)
+    assert i1["rebuilt"] == 1 and i1["n_rebuild"] == 1 and i1["cg_iters_total"] == i1["cg_iters"]
+    E2, F2, q2, i2 = ct.Potential(theta).compute(s.pos, s.types, s.box, s.pbc, warm=False)
+    assert E1 == E2 and bool((F1 == F2).all()) and bool((q1 == q2).all())
+
+
 def test_error_codes(ct, theta):
     s = G.zincblende(2, sigma=0.0)
     print("[errors]", flush=True)
