@@ -178,6 +178,28 @@ int ctbop_compute_energy_forces_charges(ctbop_ctx *ctx, int n, const double *pos
                                         double *F_dev, double *q_dev, ctbop_info *info,
                                         void *stream);
 
+/* Allocation-free form of the call above, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the per-system buffer is a library-owned device
+ * array of CTBOP_STATIC_SCRATCH_BYTES per device, held from the first call on
+ * that device until the process ends.  The caller passes inputs and outputs
+ * as above (device memory, on the current device).  The call itself
+ * allocates nothing: no hipMalloc, hipFree, pinned host memory, stream or
+ * event, and no timing events even with ctbop_profile on; its covalent
+ * kernels run on the caller's stream.  Every call starts over (state
+ * cleared, lists rebuilt, charges from zero: no warm start), so results are
+ * those of ctbop_compute_energy_forces_charges with flags = 0 on a new
+ * buffer.  All calls on one device share the one array: calls that overlap
+ * on a device (other streams, other threads, other contexts) race and give
+ * undefined results.  E_NOMEM, before any device work, when the system needs
+ * more than CTBOP_STATIC_SCRATCH_BYTES (ctbop_system_bytes() gives the need;
+ * about 12.5 KB per atom at the default capacities, so up to ~20,000 atoms). */
+#define CTBOP_STATIC_SCRATCH_BYTES (256ull << 20)
+int ctbop_compute_energy_forces_charges_static(ctbop_ctx *ctx, int n, const double *pos_dev,
+                                               const int32_t *types_dev, const double *box_host,
+                                               const int *pbc_host, double total_charge, double *E_dev,
+                                               double *F_dev, double *q_dev, ctbop_info *info, void *stream);
+
 /* Velocity-Verlet NVE for nsteps of dt_fs, re-evaluating energy, forces and
  * charges (warm-started) every step, lists rebuilt when an atom moved skin/2.
  * x_dev, v_dev (SoA, Angstrom and Angstrom/fs) are updated in place; F_dev

@@ -57,7 +57,8 @@ EXPORTS = ("ctbop_default_opts", "ctbop_create", "ctbop_destroy", "ctbop_system_
            "ctbop_compute_energy_forces_charges", "ctbop_md_run", "ctbop_status", "ctbop_last_error",
            "ctbop_debug_lists", "ctbop_profile", "ctbop_profile_classes", "ctbop_set_params", "ctbop_param_grad_bytes", "ctbop_param_grad",
            "ctbop_removal_bytes", "ctbop_removal_energies", "ctbop_md_run_nvt", "ctbop_relax_fire",
-           "ctbop_rings_bytes", "ctbop_rings", "ctbop_system_reset")
+           "ctbop_rings_bytes", "ctbop_rings", "ctbop_system_reset",
+           "ctbop_compute_energy_forces_charges_static")
 
 
 def lib():
@@ -75,6 +76,8 @@ def lib():
         L.ctbop_system_reset.argtypes = [vp, vp]
         L.ctbop_compute_energy_forces_charges.argtypes = [vp, i32, vp, vp, vp, vp, dbl, i32, vp, sz, vp, vp,
                                                           vp, ctypes.POINTER(Info), vp]
+        L.ctbop_compute_energy_forces_charges_static.argtypes = [vp, i32, vp, vp, vp, vp, dbl, vp, vp, vp,
+                                                                 ctypes.POINTER(Info), vp]
         L.ctbop_md_run.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, dbl, dbl, i32, i32, vp, sz, vp, vp, vp,
                                    ctypes.POINTER(Info), vp]
         L.ctbop_status.argtypes = [vp, vp, sz, vp, ctypes.POINTER(i32)]

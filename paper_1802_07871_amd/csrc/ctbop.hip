@@ -400,6 +400,12 @@ struct Prep {
     double *dke;
     hipStream_t st;
     bool fresh;
+    // false for the allocation-free entry point: no side stream (the
+    // covalent kernels then run on the caller's stream; results do not
+    // depend on it), the solver flag read into flag_host, and no record of
+    // the buffer in the context's maps
+    bool own = true;
+    int *flag_host = nullptr;
 };
 
 // validate, lay out, and (re)initialise the system buffer when it is new to
@@ -427,6 +433,7 @@ int prepare(ctbop_ctx *ctx, int n, const double *box, const int *pbc, void *sys,
     auto it = ctx->seen.find(sys);
     P.fresh = (it == ctx->seen.end() || !(it->second == sig));
     if (!ctx->host_flag) HIPCHK(hipHostMalloc((void **)&ctx->host_flag, 64, hipHostMallocDefault));
+    P.flag_host = ctx->host_flag;
     if (P.fresh) {
         hipLaunchKernelGGL(k_reset_state, dim3((P.L.ntile + 255) / 256), dim3(256), 0, P.st, P.L.seg.sst, P.dtiles,
                            P.L.ntile, P.dsegid);
@@ -480,19 +487,23 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
     // covalent terms on the side stream: they need only the lists and
     // overlap the assembly, the charge solve and its host round trips (a
     // fork after the sliced copy, overlapping the solve only, was slower)
-    int rc = side_stream(ctx);
-    if (rc) return rc;
-    HIPCHK(hipEventRecord(ctx->ev_fork, st));
-    HIPCHK(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
-    {
-        Timed t(ctx, 3, ctx->side);
-        hipLaunchKernelGGL((k_bond<R>), g, b, 0, ctx->side, P.dtiles, P.dseg, ctx->pd);
+    hipStream_t cst = st;
+    if (P.own) {
+        int rc = side_stream(ctx);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(ctx->ev_fork, st));
+        HIPCHK(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+        cst = ctx->side;
     }
     {
-        Timed t(ctx, 4, ctx->side);
-        hipLaunchKernelGGL((k_force_cov<R>), g, b, 0, ctx->side, P.dtiles, P.dseg, prm, 0);
+        Timed t(ctx, 3, cst);
+        hipLaunchKernelGGL((k_bond<R>), g, b, 0, cst, P.dtiles, P.dseg, ctx->pd);
     }
-    HIPCHK(hipEventRecord(ctx->ev_join, ctx->side));
+    {
+        Timed t(ctx, 4, cst);
+        hipLaunchKernelGGL((k_force_cov<R>), g, b, 0, cst, P.dtiles, P.dseg, prm, 0);
+    }
+    if (P.own) HIPCHK(hipEventRecord(ctx->ev_join, ctx->side));
     CgCtl ctl{ctx->opts.cg_tol, ctx->opts.cg_maxit};
     {
         Timed t(ctx, 2, st);
@@ -508,7 +519,9 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
     HIPCHK(hipGetLastError());
     // charge solve: launch iterations in batches, then read the convergence flag
     int done_it = 0;
-    int chunk = std::max(ctx->opts.cg_check, std::min(ctx->last_iters[P.base], ctx->opts.cg_maxit));
+    int chunk = ctx->opts.cg_check;
+    if (P.own) chunk = std::max(chunk, std::min(ctx->last_iters[P.base], ctx->opts.cg_maxit));
+    int *flag = P.flag_host;
     for (;;) {
         for (int c = 0; c < chunk; c++) {
             {
@@ -528,15 +541,15 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
         }
         done_it += chunk;
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(ctx->host_flag, &P.L.seg.sst->done, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(flag, &P.L.seg.sst->done, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (ctx->profile) ev_harvest(ctx);
-        if (ctx->host_flag[0] || done_it >= ctx->opts.cg_maxit + 1) break;
+        if (flag[0] || done_it >= ctx->opts.cg_maxit + 1) break;
         chunk = ctx->opts.cg_check;
     }
-    ctx->last_iters[P.base] = ctx->host_flag[1];
-    if (iters_out) *iters_out = ctx->host_flag[1];
-    HIPCHK(hipStreamWaitEvent(st, ctx->ev_join, 0));
+    if (P.own) ctx->last_iters[P.base] = flag[1];
+    if (iters_out) *iters_out = flag[1];
+    if (P.own) HIPCHK(hipStreamWaitEvent(st, ctx->ev_join, 0));
     {
         Timed t(ctx, 1, st);
         hipLaunchKernelGGL((k_force_coul<R, LPR>), g, b, 0, st, P.dtiles, P.dseg, ctx->pd, 0);
@@ -554,7 +567,7 @@ void lists_any(ctbop_ctx *ctx, Prep &P, int flags)
 
 int eval_any(ctbop_ctx *ctx, Prep &P, int flags, int *iters)
 {
-    ctx->eval_gen[P.base] = ctx->param_gen;
+    if (P.own) ctx->eval_gen[P.base] = ctx->param_gen;
     if (ctx->opts.fp64) return launch_eval<double>(ctx, P, ctx->pd, flags, iters);
     return launch_eval<float>(ctx, P, ctx->pf, flags, iters);
 }
@@ -1059,6 +1072,7 @@ int ctbop_debug_lists(ctbop_ctx *ctx, int n, void *sys, size_t sys_bytes, int lo
 
 } // extern "C"
 
+#include "static_entry.h"
 #include "server.h"
 #include "removal.h"
 #include "adjoint_host.h"
