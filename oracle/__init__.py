@@ -71,6 +71,11 @@ def lib():
                                         c_dbl, _dp, ctypes.c_void_p, _ipp, ctypes.POINTER(c_dbl), _ipp]
         L.oracle_param_derivative.argtypes = [c_int, _dp, _ip, _dp, _ip, _dp, c_dbl, c_dbl, c_int,
                                               c_dbl, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_eval_fq.argtypes = [c_int, _dp, _ip, _dp, _ip, _dp, c_dbl, c_dbl, c_dbl, c_int, c_int,
+                                     _dp, _dp, _dp, ctypes.c_void_p, _dp]
+        L.oracle_eval_fq.restype = c_int
+        L.oracle_eval_fq_fixed.argtypes = [c_int, _dp, _ip, _dp, _ip, _dp, c_dbl, _dp, c_int, _dp, _dp,
+                                           ctypes.c_void_p]
         L.oracle_threads.restype = c_int
         _lib = L
     return _lib
@@ -125,6 +130,44 @@ def evaluate_fixed_q(pos, types, box, pbc, params, q, method=-1, per_atom=False)
     if per_atom:
         return float(E[0]), F, eat
     return float(E[0]), F
+
+
+def evaluate_fq(pos, types, box, pbc, params, kappa, Q=0.0, tol=1e-12, maxit=5000, method=-1, q0=None,
+                per_atom=False):
+    """As evaluate(), with the charge-dependent covalent coupling f_q =
+    exp(-kappa (q_i - q_j)^2) on every bond's attraction; the charges
+    minimise the (non-quadratic) energy by nonlinear conjugate gradients."""
+    pos, types, box, pbc = _geom(pos, types, box, pbc)
+    n = len(types)
+    q = np.zeros(n) if q0 is None else np.array(q0, dtype=np.float64, copy=True)
+    E = np.zeros(1)
+    F = np.zeros((n, 3))
+    eat = np.zeros(n) if per_atom else None
+    info = np.zeros(5)
+    rc = lib().oracle_eval_fq(n, pos, types, box, pbc, np.ascontiguousarray(params, dtype=np.float64),
+                              float(kappa), float(Q), float(tol), int(maxit), int(method), q, E, F,
+                              eat.ctypes.data if per_atom else None, info)
+    if rc != 0:
+        raise RuntimeError(f"oracle charge minimisation failed (code {int(info[0])}): residual {info[1]:.3e}")
+    d = dict(iters=int(info[0]), residual=float(info[1]), mu=float(info[2]),
+             n_long=int(info[3]), n_short=int(info[4]))
+    if per_atom:
+        d["eat"] = eat
+    return float(E[0]), F, q, d
+
+
+def evaluate_fq_fixed(pos, types, box, pbc, params, kappa, q, method=-1):
+    """Energy, forces (n,3) and the charge gradient dE/dq (n,) at given
+    charges q, with the coupling of strength kappa."""
+    pos, types, box, pbc = _geom(pos, types, box, pbc)
+    n = len(types)
+    E = np.zeros(1)
+    F = np.zeros((n, 3))
+    g = np.zeros(n)
+    lib().oracle_eval_fq_fixed(n, pos, types, box, pbc, np.ascontiguousarray(params, dtype=np.float64),
+                               float(kappa), np.ascontiguousarray(q, dtype=np.float64), int(method), E, F,
+                               g.ctypes.data)
+    return float(E[0]), F, g
 
 
 def dense_h(pos, types, box, pbc, params):

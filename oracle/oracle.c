@@ -590,6 +590,222 @@ double oracle_energy_at_q(int n, const double *pos, const int *types, const doub
     return E;
 }
 
+/* ------------------------------------------------------------------------- */
+/* charge-dependent covalent coupling (stand-in f_q)                         */
+/* ------------------------------------------------------------------------- */
+
+/* The paper's potential gives its covalent bonds a covalent-ionic mixed
+ * nature through a charge function f_q (Methods, first paragraph) whose form
+ * it leaves to its predecessor.  Stand-in: the attraction of bond (i,j) is
+ * scaled by f_q = exp(-kappa (q_i - q_j)^2), so the energy is
+ *   E(x, q) = E_0(x, q) - 1/2 sum_(i,j) c_ij [f_q(q_i - q_j) - 1],
+ *   c_ij = fc(r_ij) b_ij fA(r_ij)   (charge-free attraction of the bond),
+ * with E_0 the energy without the coupling.  E is no longer quadratic in q;
+ * the charges still minimise it at fixed total charge, found by a nonlinear
+ * conjugate-gradient minimisation (Methods: the energy is minimised over the
+ * charges by conjugate gradients at every step). */
+static double fq_d1(double k, double d) { return -2.0 * k * d * exp(-k * d * d); }
+static double fq_d2(double k, double d) { return (4.0 * k * k * d * d - 2.0 * k) * exp(-k * d * d); }
+
+/* dE_c/dq added into g:  E_c = -1/2 sum_e c_e [f_q(q_i - q_j) - 1] over the
+ * ordered bonds e = (i,j) of the short list (rows = atoms) */
+static void fq_grad(int n, const nlist_t *Ls, const double *cb, double k, const double *q, double *g)
+{
+    for (int i = 0; i < n; i++)
+        for (long e = Ls->off[i]; e < Ls->off[i + 1]; e++) {
+            if (cb[e] == 0.0) continue;
+            const int j = Ls->p[e].j;
+            const double t = -0.5 * cb[e] * fq_d1(k, q[i] - q[j]);
+            g[i] += t;
+            g[j] -= t;
+        }
+}
+
+/* the full charge gradient chi + H q + dE_c/dq; hq receives chi + H q */
+static void fq_gradient(const prm_t_r *P, int n, const int *types, const nlist_t *Ll, const double *Hv,
+                        const nlist_t *Ls, const double *cb, double k, const double *q, double *hq, double *g)
+{
+    matvec_r(P, n, types, Ll, Hv, q, hq);
+    for (int i = 0; i < n; i++) {
+        hq[i] += P->sp[types[i]].chi;
+        g[i] = hq[i];
+    }
+    fq_grad(n, Ls, cb, k, q, g);
+}
+
+/* z = D^-1 (r - w 1) with w such that sum z = 0 (the projected Jacobi step).
+ * r is shifted by w in place: since sum z = 0 no dot product with z changes,
+ * and r then carries no large constant part (the multiplier mu) whose
+ * rounding would swamp those products near convergence. */
+static void fq_precond(int n, const double *dinv, double sdinv, double *r, double *z)
+{
+    double srd = 0.0;
+    for (int i = 0; i < n; i++) srd += r[i] * dinv[i];
+    const double w = srd / sdinv;
+    for (int i = 0; i < n; i++) {
+        r[i] -= w;
+        z[i] = dinv[i] * r[i];
+    }
+}
+
+/* Minimise E over q with sum q = Q by projected, Jacobi-preconditioned
+ * nonlinear conjugate gradients (Polak-Ribiere with restart at beta < 0).
+ * The step length along each direction p minimises E(q + a p) by Newton's
+ * method on phi'(a) = p.g(q) + a p.H p + p.[dE_c/dq(q + a p) - dE_c/dq(q)], with
+ * phi''(a) = p.H p - 1/2 sum_e c_e f_q''(.) (p_i - p_j)^2.  Every gradient is
+ * recomputed from its definition, so nothing drifts.  Stops when the RMS of
+ * the projected gradient is below tol.  Returns the iteration count, -1 if
+ * maxit was reached, -2 if the energy is not convex along a direction. */
+static int fq_solve(const prm_t_r *P, int n, const int *types, const nlist_t *Ll, const double *Hv,
+                    const nlist_t *Ls, const double *cb, double k, double Q, double tol, int maxit,
+                    double *q, double *res_out, double *mu_out)
+{
+    double *dinv = calloc(n, sizeof(double)), *hq = calloc(n, sizeof(double)), *g = calloc(n, sizeof(double));
+    double *r = calloc(n, sizeof(double)), *z = calloc(n, sizeof(double)), *p = calloc(n, sizeof(double));
+    double *s = calloc(n, sizeof(double)), *qa = calloc(n, sizeof(double)), *ga = calloc(n, sizeof(double));
+    double sdinv = 0.0;
+    for (int i = 0; i < n; i++) {
+        double d = P->sp[types[i]].J;
+        for (long e = Ll->off[i]; e < Ll->off[i + 1]; e++)
+            if (Ll->p[e].j == i) d += Hv[e];
+        dinv[i] = 1.0 / d;
+        sdinv += dinv[i];
+    }
+    double sq = 0.0;
+    for (int i = 0; i < n; i++) sq += q[i];
+    for (int i = 0; i < n; i++) q[i] += (Q - sq) / n;
+    fq_gradient(P, n, types, Ll, Hv, Ls, cb, k, q, hq, g);
+    for (int i = 0; i < n; i++) r[i] = -g[i];
+    fq_precond(n, dinv, sdinv, r, z);
+    double rz = 0.0;
+    for (int i = 0; i < n; i++) { p[i] = z[i]; rz += r[i] * z[i]; }
+    int it = 0, rc = -1;
+    double res = 0.0;
+    for (;;) {
+        double sr = 0.0, nr = 0.0;
+        for (int i = 0; i < n; i++) sr += r[i];
+        for (int i = 0; i < n; i++) nr += (r[i] - sr / n) * (r[i] - sr / n);
+        res = sqrt(nr / n);
+        if (res < tol) { rc = it; break; }
+        if (it >= maxit) break;
+        matvec_r(P, n, types, Ll, Hv, p, s);
+        /* phi'(0) = p.g = -p.r with the shifted r (p.(chi + H q) directly
+         * would cancel the multiplier's share in rounding) */
+        double pHp = 0.0, pr = 0.0, pg0c = 0.0;
+        for (int i = 0; i < n; i++) { pHp += p[i] * s[i]; pr += p[i] * r[i]; }
+        if (!(pHp > 0.0)) { rc = -2; break; }
+        for (int i = 0; i < n; i++) ga[i] = 0.0;
+        fq_grad(n, Ls, cb, k, q, ga);
+        for (int i = 0; i < n; i++) pg0c += p[i] * ga[i];
+        /* line search */
+        double a = 0.0;
+        int convex = 1;
+        for (int ls = 0; ls < 60; ls++) {
+            for (int i = 0; i < n; i++) { qa[i] = q[i] + a * p[i]; ga[i] = 0.0; }
+            fq_grad(n, Ls, cb, k, qa, ga);
+            double d1 = -pr + a * pHp - pg0c, d2 = pHp;
+            for (int i = 0; i < n; i++) d1 += p[i] * ga[i];
+            for (int i = 0; i < n; i++)
+                for (long e = Ls->off[i]; e < Ls->off[i + 1]; e++) {
+                    if (cb[e] == 0.0) continue;
+                    const int j = Ls->p[e].j;
+                    const double dp = p[i] - p[j];
+                    d2 += -0.5 * cb[e] * fq_d2(k, qa[i] - qa[j]) * dp * dp;
+                }
+            if (!(d2 > 0.0)) { convex = 0; break; }
+            const double step = d1 / d2;
+            a -= step;
+            if (fabs(step) <= 1e-15 * fabs(a)) break;
+        }
+        if (!convex) { rc = -2; break; }
+        for (int i = 0; i < n; i++) q[i] += a * p[i];
+        fq_gradient(P, n, types, Ll, Hv, Ls, cb, k, q, hq, g);
+        /* new residual and direction (Polak-Ribiere, restarted when negative) */
+        double *rn = ga;
+        for (int i = 0; i < n; i++) rn[i] = -g[i];
+        fq_precond(n, dinv, sdinv, rn, z);
+        double num = 0.0, rzn = 0.0;
+        for (int i = 0; i < n; i++) { num += z[i] * (rn[i] - r[i]); rzn += z[i] * rn[i]; }
+        double beta = num / rz;
+        if (beta < 0.0) beta = 0.0;
+        for (int i = 0; i < n; i++) { p[i] = z[i] + beta * p[i]; r[i] = rn[i]; }
+        rz = rzn;
+        it++;
+    }
+    double sq2 = 0.0;
+    for (int i = 0; i < n; i++) sq2 += q[i];
+    for (int i = 0; i < n; i++) q[i] += (Q - sq2) / n;
+    fq_gradient(P, n, types, Ll, Hv, Ls, cb, k, q, hq, g);
+    double mu = 0.0;
+    for (int i = 0; i < n; i++) mu += g[i];
+    if (mu_out) *mu_out = mu / n;
+    if (res_out) *res_out = res;
+    free(dinv); free(hq); free(g); free(r); free(z); free(p); free(s); free(qa); free(ga);
+    return rc;
+}
+
+/* Full evaluation with the charge coupling of strength kappa (arguments and
+ * info as for oracle_eval; info[0] = -2 if the energy was not convex in q
+ * along a search direction).  kappa = 0 reduces to the quadratic energy. */
+int oracle_eval_fq(int n, const double *pos, const int *types, const double *box, const int *pbc,
+                   const double *params, double kappa, double Q, double tol, int maxit, int method,
+                   double *q_io, double *E, double *F, double *eat, double *info)
+{
+    prm_t_r P;
+    read_params_r(params, -1, 0.0, &P);
+    cell_t c;
+    cell_init(&c, box, pbc);
+    nlist_t Ll, Ls;
+    nl_build(&c, n, pos, P.rc, method, &Ll);
+    nl_filter(&Ll, short_cut(&P), &Ls);
+    double *Hv = malloc(sizeof(double) * (Ll.off[n] > 0 ? Ll.off[n] : 1));
+    double *cb = calloc(Ls.off[n] > 0 ? Ls.off[n] : 1, sizeof(double));
+    assemble_r(&P, n, types, &Ll, Hv);
+    covalent_q_r(&P, n, types, &Ls, NULL, 0.0, cb, NULL, NULL);      /* c_e only */
+    double res = 0.0, mu = 0.0;
+    int it = fq_solve(&P, n, types, &Ll, Hv, &Ls, cb, kappa, Q, tol, maxit, q_io, &res, &mu);
+    if (F) memset(F, 0, sizeof(double) * 3 * n);
+    double *ea = calloc(n, sizeof(double));
+    double Ec = covalent_q_r(&P, n, types, &Ls, q_io, kappa, NULL, ea, F);
+    double Eq = charge_terms_r(&P, n, types, &Ll, q_io, ea, F);
+    *E = Ec + Eq;
+    if (eat) memcpy(eat, ea, sizeof(double) * n);
+    if (info) {
+        info[0] = it; info[1] = res; info[2] = mu;
+        info[3] = (double)Ll.off[n]; info[4] = (double)Ls.off[n];
+    }
+    free(ea); free(Hv); free(cb);
+    nl_free(&Ll); nl_free(&Ls);
+    return it >= 0 ? 0 : 1;
+}
+
+/* Energy, forces and the charge gradient g = dE/dq at given charges q, with
+ * the coupling of strength kappa (no charge minimisation). */
+int oracle_eval_fq_fixed(int n, const double *pos, const int *types, const double *box, const int *pbc,
+                         const double *params, double kappa, const double *q, int method, double *E,
+                         double *F, double *g)
+{
+    prm_t_r P;
+    read_params_r(params, -1, 0.0, &P);
+    cell_t c;
+    cell_init(&c, box, pbc);
+    nlist_t Ll, Ls;
+    nl_build(&c, n, pos, P.rc, method, &Ll);
+    nl_filter(&Ll, short_cut(&P), &Ls);
+    double *Hv = malloc(sizeof(double) * (Ll.off[n] > 0 ? Ll.off[n] : 1));
+    double *cb = calloc(Ls.off[n] > 0 ? Ls.off[n] : 1, sizeof(double));
+    double *hq = calloc(n, sizeof(double));
+    assemble_r(&P, n, types, &Ll, Hv);
+    if (F) memset(F, 0, sizeof(double) * 3 * n);
+    double Ec = covalent_q_r(&P, n, types, &Ls, q, kappa, cb, NULL, F);
+    double Eq = charge_terms_r(&P, n, types, &Ll, q, NULL, F);
+    *E = Ec + Eq;
+    if (g) fq_gradient(&P, n, types, &Ll, Hv, &Ls, cb, kappa, q, hq, g);
+    free(Hv); free(cb); free(hq);
+    nl_free(&Ll); nl_free(&Ls);
+    return 0;
+}
+
 /* Velocity-Verlet NVE: half kick, drift, new forces (charges re-equilibrated,
  * warm-started), half kick.  Fixed atoms (fixed[i] != 0) neither move nor
  * change velocity but still interact.  Velocities in Angstrom/fs.

@@ -26,7 +26,9 @@
  * Charges minimise E over q with sum q = Q (Methods: charges are minimised by
  * conjugate gradients at every step).  E is quadratic in q, so the minimiser
  * solves H q + chi = mu 1, 1^T q = Q with H = diag(J) + [C_ij summed over
- * images].
+ * images].  With the optional charge-dependent coupling of the covalent part
+ * (covalent_q below) E is no longer quadratic in q; oracle.c minimises it by
+ * nonlinear conjugate gradients.
  */
 
 /* ------------------------------------------------------------------------- */
@@ -193,9 +195,17 @@ static SC FN(coul)(const FN(prm_t) *P, int ti, int tj, double r, SC *dC)
  * largest S of the potential).  Writes per-atom energy (may be NULL) and adds
  * forces into F (n x 3, may be NULL).  Plain double loop over bonds and their
  * k environment; forces by the chain rule through fc, fR, fA, b, zeta_l,
- * cos(theta) and the radial exponential. */
-static SC FN(covalent)(const FN(prm_t) *P, int n, const int *types, const nlist_t *L,
-                       SC *eat, SC *F)
+ * cos(theta) and the radial exponential.
+ *
+ * Charge-dependent coupling (Methods, first paragraph: the covalent-ionic
+ * mixed bond nature is expressed by a charge function f_q whose form this
+ * paper does not give; the stand-in here): with charges qf != NULL, the
+ * attraction of bond (i,j) is scaled by f_q = exp(-kq (q_i - q_j)^2), i.e.
+ * the bond energy is 1/2 fc (fR - b fA f_q).  Forces are taken at fixed
+ * charges.  cb (may be NULL) receives, for every list entry e of a bond, the
+ * charge-free attraction c_e = fc b fA (0 for entries beyond S). */
+static SC FN(covalent_q)(const FN(prm_t) *P, int n, const int *types, const nlist_t *L,
+                         const double *qf, double kq, double *cb, SC *eat, SC *F)
 {
     SC Etot = 0.0;
     (void)n;
@@ -208,6 +218,7 @@ static SC FN(covalent)(const FN(prm_t) *P, int n, const int *types, const nlist_
             const int j = L->p[e].j;
             const double r = L->p[e].r;
             FN(pair_t) pj = FN(pair_params)(P, ti, types[j]);
+            if (cb) cb[e] = 0.0;
             if (r >= RE(pj.S)) continue;
             const double *dv = L->p[e].d;
             double u[3] = {dv[0] / r, dv[1] / r, dv[2] / r};
@@ -229,16 +240,22 @@ static SC FN(covalent)(const FN(prm_t) *P, int n, const int *types, const nlist_
             SC b = FN(bond_order)(si, P->p, z, db);
             SC f = FN(fc)(r, pj.R, pj.S), df = FN(dfc)(r, pj.R, pj.S);
             SC fR = pj.A * SEXP(-pj.lam1 * r), fA = pj.B * SEXP(-pj.lam2 * r);
-            ei += 0.5 * f * (fR - b * fA);
+            double fq = 1.0;
+            if (qf) {
+                const double dq = qf[i] - qf[j];
+                fq = exp(-kq * dq * dq);
+            }
+            if (cb) cb[e] = RE(f * b * fA);
+            ei += 0.5 * f * (fR - b * fA * fq);
             if (!F) continue;
-            /* pair part: dV/dr at fixed b */
-            SC dVdr = 0.5 * (df * (fR - b * fA) + f * (-pj.lam1 * fR + b * pj.lam2 * fA));
+            /* pair part: dV/dr at fixed b (and fixed charges) */
+            SC dVdr = 0.5 * (df * (fR - b * fA * fq) + f * (-pj.lam1 * fR + b * fq * pj.lam2 * fA));
             for (int a = 0; a < 3; a++) {
                 F[3 * i + a] += dVdr * u[a];
                 F[3 * j + a] -= dVdr * u[a];
             }
-            /* bond-order part: P_l = dV/dzeta_l = -1/2 fc fA db/dzeta_l */
-            SC Pl[2] = {-0.5 * f * fA * db[0], -0.5 * f * fA * db[1]};
+            /* bond-order part: P_l = dV/dzeta_l = -1/2 fc fA f_q db/dzeta_l */
+            SC Pl[2] = {-0.5 * f * fA * fq * db[0], -0.5 * f * fA * fq * db[1]};
             for (long e2 = L->off[row]; e2 < L->off[row + 1]; e2++) {
                 if (e2 == e) continue;
                 const int k = L->p[e2].j;
@@ -272,6 +289,12 @@ static SC FN(covalent)(const FN(prm_t) *P, int n, const int *types, const nlist_
         Etot += ei;
     }
     return Etot;
+}
+
+static SC FN(covalent)(const FN(prm_t) *P, int n, const int *types, const nlist_t *L,
+                       SC *eat, SC *F)
+{
+    return FN(covalent_q)(P, n, types, L, NULL, 0.0, NULL, eat, F);
 }
 
 /* ------------------------------------------------------------------------- */
