@@ -110,6 +110,17 @@ typedef struct {
     int    short_cap;  /* covalent-list entries per atom (0: 64)                                  */
     int    fp64;       /* 1: every pair/triplet term in FP64 (default 0: FP32 terms, FP64 sums)   */
     int    cg_check;   /* charge-solve iterations launched between convergence checks (0: 4)    */
+    double fq_kappa;   /* charge-dependent covalent coupling (e^-2, >= 0; default 0 = off): the
+                          paper's covalent-ionic mixed bond function f_q (Methods, first
+                          paragraph) has its form in the authors' earlier paper; the stand-in
+                          scales the attraction of every bond (i,j) by exp(-fq_kappa (q_i -
+                          q_j)^2), so the bond energy is 1/2 fc (fR - b_ij fA f_q).  The energy
+                          is then not quadratic in q; the charges minimise it by projected,
+                          preconditioned nonlinear conjugate gradients (Polak-Ribiere, Newton
+                          line search) to the same cg_tol on the projected gradient.  Forces
+                          are taken at the minimising charges.  Single-system evaluation, MD,
+                          NVT, relaxation and the allocation-free call support it; the server,
+                          the removal energies and the parameter adjoint return E_INVAL.      */
 } ctbop_opts;
 
 typedef struct {

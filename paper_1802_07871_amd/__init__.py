@@ -36,7 +36,7 @@ class CtbopError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int), ("skin", ctypes.c_double),
                 ("long_cap", ctypes.c_int), ("short_cap", ctypes.c_int), ("fp64", ctypes.c_int),
-                ("cg_check", ctypes.c_int)]
+                ("cg_check", ctypes.c_int), ("fq_kappa", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -148,7 +148,8 @@ class Potential:
     """A parameter set and solver options (a ctbop_ctx)."""
 
     def __init__(self, params=None, cg_tol: float = 1e-9, cg_maxit: int = 500, skin: float = 0.5,
-                 long_cap: int = 512, short_cap: int = 64, fp64: bool = False, cg_check: int = 4):
+                 long_cap: int = 512, short_cap: int = 64, fp64: bool = False, cg_check: int = 4,
+                 fq_kappa: float = 0.0):
         if params is None:
             from ctbop_inputs import params as _p
             params = _p.load()
@@ -156,7 +157,7 @@ class Potential:
         if th.shape != (N_PARAMS,):
             raise ValueError("expected 56 parameters")
         self.params = th
-        self.opts = Opts(cg_tol, cg_maxit, skin, long_cap, short_cap, int(bool(fp64)), cg_check)
+        self.opts = Opts(cg_tol, cg_maxit, skin, long_cap, short_cap, int(bool(fp64)), cg_check, float(fq_kappa))
         h = ctypes.c_void_p()
         _check(lib().ctbop_create(th.ctypes.data, N_PARAMS, ctypes.byref(self.opts), ctypes.byref(h)))
         self.ctx = h

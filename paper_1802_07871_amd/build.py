@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libctbop.so")
 SOURCES = ["ctbop.hip", "ctbop_dev.h", "k_lists.h", "k_tersoff.h", "k_qeq.h", "k_md.h", "server.h", "dual.h",
-           "k_adjoint.h", "adjoint_host.h", "removal.h", "k_rings.h", "rings_host.h", "static_entry.h"]
+           "k_adjoint.h", "adjoint_host.h", "removal.h", "k_rings.h", "rings_host.h", "static_entry.h", "k_fq.h"]
 
 
 def hipcc_cmd(out: str) -> list[str]:

@@ -242,6 +242,7 @@ int ctbop_param_grad(ctbop_ctx *ctx, int n, const double *box, const int *pbc, v
                      double *grad_host, int *cg_iters, void *stream)
 {
     if (!ctx || !sys || !adj_ws || !dL_dF_dev || !grad_host) return fail(CTBOP_E_INVAL, "null argument");
+    if (ctx->opts.fq_kappa > 0.0) return fail(CTBOP_E_INVAL, "parameter adjoint: not available with fq_kappa > 0");
     auto it = ctx->seen.find(sys);
     auto ge = ctx->eval_gen.find(sys);
     if (it == ctx->seen.end() || it->second.n != n || ge == ctx->eval_gen.end() || ge->second != ctx->param_gen)

@@ -20,6 +20,7 @@
 #include "k_tersoff.h"
 #include "k_qeq.h"
 #include "k_md.h"
+#include "k_fq.h"
 
 using namespace ctbop;
 
@@ -234,6 +235,14 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
     size_t o_qs = take(8 * (size_t)n), o_qh1 = take(8 * (size_t)n), o_qh2 = take(8 * (size_t)n),
            o_qh3 = take(8 * (size_t)n);
     size_t o_part = take(8 * NPART * (size_t)S.ntile);
+    const bool fq = ctx->opts.fq_kappa > 0.0;
+    size_t o_rl = 0, o_rold = 0, o_wq = 0;
+    if (fq) {
+        o_rl = take(8 * np);
+        o_rold = take(8 * np);
+        o_wq = take(8 * np * S.Wb);
+    }
+    S.fqk = ctx->opts.fq_kappa;
     L.bytes = o;
     L.ntile = S.ntile;
     if (base) {
@@ -281,6 +290,11 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
         S.q_h3 = (double *)(base + o_qh3);
         S.part = (double *)(base + o_part);
         S.sst = (SegState *)(base + L.off_sst);
+        if (fq) {
+            S.rl = (double *)(base + o_rl);
+            S.rold = (double *)(base + o_rold);
+            S.wq = (double *)(base + o_wq);
+        }
     }
     return CTBOP_OK;
 }
@@ -495,11 +509,17 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
         HIPCHK(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
         cst = ctx->side;
     }
+    // with the charge coupling the covalent gather needs the charges: the
+    // side stream then runs the bond pass and the coupling weights only, and
+    // the gather follows the solve on the caller's stream
+    const bool fq = ctx->opts.fq_kappa > 0.0;
     {
         Timed t(ctx, 3, cst);
         hipLaunchKernelGGL((k_bond<R>), g, b, 0, cst, P.dtiles, P.dseg, ctx->pd);
     }
-    {
+    if (fq) {
+        hipLaunchKernelGGL((k_fq_weight<R>), g, b, 0, cst, P.dtiles, P.dseg);
+    } else {
         Timed t(ctx, 4, cst);
         hipLaunchKernelGGL((k_force_cov<R>), g, b, 0, cst, P.dtiles, P.dseg, prm, 0);
     }
@@ -508,6 +528,11 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
     {
         Timed t(ctx, 2, st);
         hipLaunchKernelGGL((k_assemble<R, LPR>), g, b, 0, st, P.dtiles, P.dseg, ctx->pd);
+    }
+    if (fq) {
+        // the starting residual needs the coupling weights of this step
+        if (P.own) HIPCHK(hipStreamWaitEvent(st, ctx->ev_join, 0));
+        hipLaunchKernelGGL(k_fq_r0, g, b, 0, st, P.dtiles, P.dseg);
     }
     {
         Timed t(ctx, 8, st);
@@ -527,6 +552,24 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
             {
                 Timed t(ctx, 6, st);
                 hipLaunchKernelGGL(k_cg_dir, g, b, 0, st, P.dtiles, P.dseg);
+            }
+            if (fq) {
+                {
+                    Timed t(ctx, 0, st);
+                    hipLaunchKernelGGL((k_spmv<R, SPMV_U, true>), g, b, 0, st, P.dtiles, P.dseg);
+                }
+                // two Newton steps on the step length
+                for (int pass = 0; pass < 2; pass++) {
+                    hipLaunchKernelGGL(k_fq_ls, g, b, 0, st, P.dtiles, P.dseg, pass);
+                    hipLaunchKernelGGL(k_fq_fin_ls, g1, b, 0, st, sid, P.dseg, pass);
+                }
+                hipLaunchKernelGGL(k_fq_step, g, b, 0, st, P.dtiles, P.dseg);
+                {
+                    Timed t(ctx, 5, st);
+                    hipLaunchKernelGGL(k_fq_resid, g, b, 0, st, P.dtiles, P.dseg);
+                }
+                hipLaunchKernelGGL(k_fq_fin_update, g1, b, 0, st, sid, P.dseg, ctl);
+                continue;
             }
             {
                 Timed t(ctx, 0, st);
@@ -549,7 +592,12 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
     }
     if (P.own) ctx->last_iters[P.base] = flag[1];
     if (iters_out) *iters_out = flag[1];
-    if (P.own) HIPCHK(hipStreamWaitEvent(st, ctx->ev_join, 0));
+    if (P.own && !fq) HIPCHK(hipStreamWaitEvent(st, ctx->ev_join, 0));
+    if (fq) {
+        hipLaunchKernelGGL((k_fq_scale<R>), g, b, 0, st, P.dtiles, P.dseg);
+        Timed t(ctx, 4, st);
+        hipLaunchKernelGGL((k_force_cov<R>), g, b, 0, st, P.dtiles, P.dseg, prm, 0);
+    }
     {
         Timed t(ctx, 1, st);
         hipLaunchKernelGGL((k_force_coul<R, LPR>), g, b, 0, st, P.dtiles, P.dseg, ctx->pd, 0);
@@ -625,6 +673,7 @@ void ctbop_default_opts(ctbop_opts *o)
     o->short_cap = 64;
     o->fp64 = 0;
     o->cg_check = 4;
+    o->fq_kappa = 0.0;
 }
 
 int ctbop_create(const double *params, int n_params, const ctbop_opts *opts, ctbop_ctx **out)
@@ -649,6 +698,10 @@ int ctbop_create(const double *params, int n_params, const ctbop_opts *opts, ctb
     if (c->opts.short_cap > 255) {
         delete c;
         return fail(CTBOP_E_INVAL, "short_cap must be <= 255");
+    }
+    if (!(c->opts.fq_kappa >= 0.0)) {
+        delete c;
+        return fail(CTBOP_E_INVAL, "fq_kappa must be >= 0");
     }
     fill_params<float>(c->theta, c->opts, c->pf);
     fill_params<double>(c->theta, c->opts, c->pd);

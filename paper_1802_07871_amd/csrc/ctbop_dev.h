@@ -78,6 +78,9 @@ struct SegState {
     double nnz_coul;                          // Coulomb entries inside rc at the last assembly
     double nnz_wide;                          // of which in slices that keep full entries
     double nnz_slots;                         // entry slots the sliced product reads: 64 x longest row, per slice
+    // charge coupling (f_q) solve: p^T r, p^T H p and the coupling part of
+    // phi'(0) along the current direction (line search)
+    double pr, ps, A0;
 };
 
 // ---------------------------------------------------------------------------
@@ -170,6 +173,15 @@ struct Seg {
     double *q_h1, *q_h2, *q_h3;   // the three solves before it (predictor history) [n]
     double *part;      // [NPART * ntile]: partial k of tile t at k * ntile + t
     SegState *sst;
+    // Charge-dependent coupling of the covalent part (fqk > 0; null arrays
+    // otherwise): the bond attraction is scaled by f_q = exp(-fqk (q_i - q_j)^2).
+    // rl holds the quadratic part of the residual, -(H q + chi) + shift, kept
+    // by recursion; rold the last full residual (for the Polak-Ribiere
+    // coefficient); wq per bond (sliced like the bond rows) the symmetrised
+    // charge-free attraction (c_ij + c_ji)/2, c = fc b fA.
+    double fqk;
+    double *rl, *rold;  // [npad]
+    double *wq;         // [npad * Wb]
 };
 
 struct Tile {
@@ -356,6 +368,19 @@ __device__ __forceinline__ void tile_partials(const Seg &S, int tile_local, doub
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < K; k++) S.part[(size_t)k * S.ntile + tile_local] = tot[k];
+    }
+}
+
+// The same, written as partials k0 .. k0+K-1 (so that two kernels can leave
+// their sums for one finalize).
+template <int K>
+__device__ __forceinline__ void tile_partials_at(const Seg &S, int tile_local, double (&v)[K], double *lds, int k0)
+{
+    double tot[K];
+    block_sum<K>(v, lds, tot);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; k++) S.part[(size_t)(k0 + k) * S.ntile + tile_local] = tot[k];
     }
 }
 

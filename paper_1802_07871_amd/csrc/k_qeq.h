@@ -455,8 +455,10 @@ __global__ void __launch_bounds__(TILE) k_shift_stats(const Tile *tiles, Seg *se
     const float *binv = S.binv;
     double r = 0.0;
     if (live) {
-        r = rv[s] - S.sst->w;
+        const double w = S.sst->w;
+        r = rv[s] - w;
         rv[s] = r;
+        if (S.rl) S.rl[s] -= w;              // f_q coupling: the quadratic part too
     }
     const double y = block_apply(binv, s, r);
     double v[4] = {0, 0, 0, 0};
@@ -508,6 +510,7 @@ __global__ void __launch_bounds__(TILE) k_cg_dir(const Tile *tiles, Seg *segs)
     const double r = rv[s] - w;
     rv[s] = r;
     pv[s] = (y - w * m1) + beta * p;
+    if (S.rl) S.rl[s] -= w;                  // f_q coupling: the quadratic part too
 }
 
 // s = H p and the tile's share of p^T s, one row per lane; U entries of the
@@ -548,16 +551,18 @@ __device__ __forceinline__ double spmv_row(const double *p_, const IDX *row_, co
 // summed, so U gathers of p are in flight per lane (U accumulators, combined
 // in a fixed order at the end).  A slice reads 16-bit row offsets (6 bytes
 // per entry) unless it needs the full entries.
-template <typename R, int U>
+// With FQ (the f_q coupling's nonlinear solve) the tile's share of p^T r
+// comes along as a second partial, for the line search.
+template <typename R, int U, bool FQ = false>
 __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
 {
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     if (S.sst->done) return;
-    __shared__ double lds[4];
+    __shared__ double lds[4 * 2];
     const int slot = T.row0 + threadIdx.x;
     const int s = T.row0 + S.hperm[slot];
-    double pap = 0.0;
+    double pap = 0.0, pr = 0.0;
     if (s < S.n) {
         const size_t b0 = slice_base(slot, S.Wl);
         const R *hrow = reinterpret_cast<const R *>(S.H) + b0;
@@ -569,9 +574,15 @@ __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
         const double y = S.jd[s] * ps + a;
         S.s[s] = y;
         pap = ps * y;
+        if (FQ) pr = ps * S.r[s];
     }
-    double v[1] = {pap};
-    tile_partials<1>(S, T.row0 / TILE, v, lds);
+    if (FQ) {
+        double v[2] = {pap, pr};
+        tile_partials<2>(S, T.row0 / TILE, v, lds);
+    } else {
+        double v[1] = {pap};
+        tile_partials<1>(S, T.row0 / TILE, v, lds);
+    }
 }
 
 // alpha = rho / p^T H p

@@ -5,8 +5,9 @@
 //     zeta_l,ij = sum_{k != j} fc(r_ik) w_l(cos theta_ijk) exp[(alpha_l (r_ij - r_ik))^3]
 // (Methods, Eq. 2, one per channel), the vectorised bond order
 //     b_ij = G (sum_l (g_l + zeta_l^n_l)^-p)^(1/(2 sigma p))       (Eqs. 3-5, 7)
-// and the bond energy 1/2 fc (fR - b fA).  Per entry it stores b_ij and the
-// coefficients P_l = dE/dzeta_l,ij = -1/2 fc fA db/dzeta_l.
+// and the bond energy 1/2 fc (fR - b fA).  Per entry it stores b_ij, the
+// coefficients P_l = dE/dzeta_l,ij = -1/2 fc fA db/dzeta_l and the bond's
+// attraction c_ij = fc b fA (which the charge coupling f_q scales).
 //
 // Force gather (one lane per sorted atom m) writes only F_m: every covalent
 // term that moves with x_m, read back from the stored coefficients:
@@ -291,7 +292,7 @@ __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Par
         out.x = (R)b;
         out.y = (R)(-0.5 * fc * fA * db1);
         out.z = (R)(-0.5 * fc * fA * db2);
-        out.w = (R)0;
+        out.w = (R)(fc * b * fA);                // the charge-free attraction (f_q coupling)
         st4<R>(slot, (size_t)e * SLICE, out);
     }
     S.ecov[s] = ecov;

@@ -21,6 +21,7 @@ int ctbop_removal_bytes(ctbop_ctx *ctx, int n, const double *box, const int *pbc
 {
     if (!ctx || !box || !pbc || !bytes) return fail(CTBOP_E_INVAL, "null argument");
     if (n < 2 || m < 0) return fail(CTBOP_E_INVAL, "need n >= 2 and m >= 0");
+    if (ctx->opts.fq_kappa > 0.0) return fail(CTBOP_E_INVAL, "removal energies: not available with fq_kappa > 0");
     Layout L;
     int rc = make_layout(ctx, n, box, pbc, nullptr, L);
     if (rc) return rc;

@@ -453,6 +453,7 @@ int ctbop_server_create(ctbop_ctx *ctx, void *arena, size_t arena_bytes, int max
                         void *stream, ctbop_server **out)
 {
     if (!ctx || !arena || !out || max_slots <= 0) return fail(CTBOP_E_INVAL, "bad argument");
+    if (ctx->opts.fq_kappa > 0.0) return fail(CTBOP_E_INVAL, "server: not available with fq_kappa > 0");
     ctbop_server *S = new ctbop_server();
     S->ctx = ctx;
     S->arena = (char *)arena;
