@@ -26,6 +26,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+# VALU lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (an FMA
+# is one operation; FP32 157.3 TFLOP/s = 2 x 2 (packed) x this, FP64 78.6 = 2 x this)
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# Algorithmic lane operations of the force kernels (add, mul, FMA, conversion,
+# square root or transcendental = 1), counted from the formulas each evaluates:
+#   Coulomb force gather, per pair inside rc: pair vector and distance 11,
+#     C and (dC/dr)/r in FP64 35, force and energy sums 11
+#   bond pass (FP64), per bond: geometry and cutoff 16, bond order 25, pair
+#     terms and coefficients 20; per ordered triplet (i; j, k): cosine 5, two
+#     angular values 14, environment sums 2
+#   covalent gather (FP32), per bond: own pair term 22, as partner 31; per
+#     ordered triplet: the gradient pair as centre 105, as partner and as
+#     environment 208
+OPS_COUL_PAIR = 57
+OPS_BOND = (61, 21)            # per bond, per triplet
+OPS_COV = (53, 313)            # per bond, per triplet
 KERNEL_SOURCES = ["ctbop_dev.h", "k_qeq.h", "k_tersoff.h", "k_lists.h", "ctbop.hip"]
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_spmv_step1m.md")
 KERNEL_TABLE_STEPS = 10
@@ -354,6 +370,25 @@ def rings_bench(ct, theta):
     return out
 
 
+def valu_model(kernels, pairs, bonds, trips):
+    """Algorithmic VALU rate of the force kernels: their operation counts
+    (OPS_* above) for this step's pairs, bonds and triplets over the average
+    launch time, against the VALU lane-operation peak."""
+    out = {}
+    for name, ops in (("force_coul", OPS_COUL_PAIR * pairs),
+                      ("bond", OPS_BOND[0] * bonds + OPS_BOND[1] * trips),
+                      ("force_cov", OPS_COV[0] * bonds + OPS_COV[1] * trips)):
+        k = kernels.get(name)
+        if not k or not k["launches"]:
+            continue
+        t = k["avg_us"] * 1e-6
+        out[name] = {"bound": "alu", "ops_per_launch": float(ops), "achieved": ops / t / 1e12,
+                     "peak": VALU_PEAK_OPS / 1e12, "unit": "T lane-op/s", "frac": ops / t / VALU_PEAK_OPS,
+                     "avg_launch_us": k["avg_us"]}
+    out["counts"] = {"coulomb_pairs": pairs, "bonds": bonds, "triplets": trips}
+    return out
+
+
 def measure_copy_peak(torch, mib: int = 2048, reps: int = 10):
     """Device-to-device copy bandwidth on this GPU (read + write bytes per
     second, best of `reps` copies of `mib` MiB), the practical HBM ceiling
@@ -559,6 +594,7 @@ def main():
                            "frac": (force_bytes / f_avg / 1e9) / HBM_PEAK_GBS if fcnt else None,
                            "kernel": "k_force_coul", "bytes_per_launch": force_bytes,
                            "avg_launch_us": f_avg * 1e6},
+        "valu_model": valu_model(kernels, nnz, int(info["n_bonds"]), int(info["n_triplets"])),
         "kernels": kernels,
         "kernels_note": f"per-kernel event times from {KERNEL_TABLE_STEPS} steps after the timed region "
                         "(in it only k_spmv and k_force_coul are timed)",

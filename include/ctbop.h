@@ -142,6 +142,10 @@ typedef struct {
                                          solver's sliced copy (the rest: 16-bit offsets) */
     unsigned long long nnz_coul_slots; /* entry slots the solver's product reads: per
                                           slice of 64 rows, 64 x its longest row */
+    unsigned long long n_bonds;        /* covalent bonds (ordered pairs inside S_ij) at the
+                                          last evaluation                              */
+    unsigned long long n_triplets;     /* ordered bond pairs (i; j, k), j != k, sharing
+                                          the centre i: the zeta_l terms (Eq. 2)        */
 } ctbop_info;
 
 /* Fill *o with the defaults above. */

@@ -232,8 +232,7 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
     size_t o_ecov = take(8 * np), o_fcov = take(8 * 3 * np);
     size_t o_q = take(8 * np), o_r = take(8 * np), o_p = take(8 * np), o_s = take(8 * np), o_jd = take(8 * np);
     size_t o_binv = take(4 * np * BK), o_m1 = take(8 * np), o_y = take(8 * np);
-    size_t o_qs = take(8 * (size_t)n), o_qh1 = take(8 * (size_t)n), o_qh2 = take(8 * (size_t)n),
-           o_qh3 = take(8 * (size_t)n);
+    size_t o_qs = take(8 * (size_t)n), o_qring = take(8 * (size_t)NHIST * n);
     size_t o_part = take(8 * NPART * (size_t)S.ntile);
     const bool fq = ctx->opts.fq_kappa > 0.0;
     size_t o_rl = 0, o_rold = 0, o_wq = 0;
@@ -285,9 +284,7 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
         S.y = (double *)(base + o_y);
         S.jd = (double *)(base + o_jd);
         S.q_state = (double *)(base + o_qs);
-        S.q_h1 = (double *)(base + o_qh1);
-        S.q_h2 = (double *)(base + o_qh2);
-        S.q_h3 = (double *)(base + o_qh3);
+        S.q_ring = (double *)(base + o_qring);
         S.part = (double *)(base + o_part);
         S.sst = (SegState *)(base + L.off_sst);
         if (fq) {
@@ -656,6 +653,8 @@ int fill_info(ctbop_ctx *ctx, Prep &P, ctbop_info *info)
     info->nnz_coul = (unsigned long long)ss.nnz_coul;
     info->nnz_coul_wide = (unsigned long long)ss.nnz_wide;
     info->nnz_coul_slots = (unsigned long long)ss.nnz_slots;
+    info->n_bonds = (unsigned long long)ss.nbond;
+    info->n_triplets = (unsigned long long)ss.ntrip;
     if (ss.status) return fail(info->status, status_text(ss.status));
     return CTBOP_OK;
 }

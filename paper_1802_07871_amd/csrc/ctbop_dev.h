@@ -24,6 +24,8 @@ constexpr int MAX_ATOMS = (1 << CODE_SHIFT) - 1;
 constexpr int SLICE = 64;              // rows per slice of the sliced list layout (one wave)
 constexpr int BK = 16;                 // rows per block of the block-Jacobi preconditioner
 constexpr int WB = 32;                 // bond-row capacity (bonds inside S_ij per atom)
+constexpr int NHIST = 3;               // charge solutions kept before the latest (predictor history)
+constexpr int PRED_ORDER = 4;          // points of the starting-charge extrapolation (1..NHIST+1)
 
 // status bits (mapped to CTBOP_E_* codes on the host)
 constexpr int ST_TOO_CLOSE = 1, ST_NOCONV = 2, ST_NOT_PD = 4, ST_OVERFLOW = 8, ST_REV = 16;
@@ -61,7 +63,8 @@ struct SegState {
     int status;        // ST_* bits, sticky until the next rebuild/call reset
     int maxl, maxs;    // largest list rows at the last build
     int built;         // lists exist
-    int nhist;         // charge solutions kept for the starting-charge predictor (0..4)
+    int nhist;         // charge solutions kept for the starting-charge predictor (0..NHIST+1)
+    int qhead;         // ring slot of the solution before the latest
     int warm;          // per-segment start mode when a launch passes warm < 0 (serving)
     int forces_done;   // serving: forces and energy of the current request are written
     int nrebuild;      // rebuilds since the system buffer was set up
@@ -78,6 +81,7 @@ struct SegState {
     double nnz_coul;                          // Coulomb entries inside rc at the last assembly
     double nnz_wide;                          // of which in slices that keep full entries
     double nnz_slots;                         // entry slots the sliced product reads: 64 x longest row, per slice
+    double nbond, ntrip;                      // bonds and ordered bond pairs (i; j, k) at the last evaluation
     // charge coupling (f_q) solve: p^T r, p^T H p and the coupling part of
     // phi'(0) along the current direction (line search)
     double pr, ps, A0;
@@ -170,7 +174,7 @@ struct Seg {
     float *binv;       // [npad * BK]
     double *m1, *y;    // [npad]
     double *q_state;   // user order charges of the last solve, for the warm start [n]
-    double *q_h1, *q_h2, *q_h3;   // the three solves before it (predictor history) [n]
+    double *q_ring;    // the NHIST solves before it, a ring of [NHIST][n] (predictor history; null: none)
     double *part;      // [NPART * ntile]: partial k of tile t at k * ntile + t
     SegState *sst;
     // Charge-dependent coupling of the covalent part (fqk > 0; null arrays

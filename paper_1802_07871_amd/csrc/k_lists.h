@@ -190,8 +190,15 @@ __global__ void k_cell_sort(const Tile *tiles, Seg *segs)
 // Local coordinates of every sorted atom for this call's positions, and the
 // starting charges in the sorted frame (with their sum, for the projection).
 // warm: 0 = zeros, 1 = the last solution, 2 = extrapolate the last solutions
-// by the polynomial through as many as are kept (cubic through four, else
-// quadratic through three, linear through two), for consecutive MD steps.
+// by the polynomial through the last m of them (m = min(kept, PRED_ORDER)),
+// for consecutive MD steps: the value at the next step of the polynomial of
+// degree m-1 through q_0, q_-1, ..., q_-(m-1) is sum_k (-1)^k C(m, k+1) q_-k.
+__device__ __forceinline__ double pred_coef(int m, int k)
+{
+    // (-1)^k C(m, k+1) for m <= 4
+    constexpr double C[5][4] = {{0, 0, 0, 0}, {1, 0, 0, 0}, {2, 1, 0, 0}, {3, 3, 1, 0}, {4, 6, 4, 1}};
+    return (k & 1) ? -C[m][k] : C[m][k];
+}
 template <typename R>
 __global__ void k_gather(const Tile *tiles, Seg *segs, int warm)
 {
@@ -216,11 +223,17 @@ __global__ void k_gather(const Tile *tiles, Seg *segs, int warm)
         if ((void *)S.xs64 != S.xs) S.xs64[s] = w;
         const int wm = warm < 0 ? S.sst->warm : warm;
         if (wm) {
-            const int nh = wm == 2 ? S.sst->nhist : 1;
-            if (nh >= 4) q0 = 4.0 * S.q_state[i] - 6.0 * S.q_h1[i] + 4.0 * S.q_h2[i] - S.q_h3[i];
-            else if (nh == 3) q0 = 3.0 * S.q_state[i] - 3.0 * S.q_h1[i] + S.q_h2[i];
-            else if (nh == 2) q0 = 2.0 * S.q_state[i] - S.q_h1[i];
-            else if (nh == 1) q0 = S.q_state[i];
+            int m = 1;
+            if (wm == 2) m = min(S.sst->nhist, (S.q_ring ? NHIST : 0) + 1);
+            m = min(m, PRED_ORDER);
+            if (m >= 1) {
+                q0 = pred_coef(m, 0) * S.q_state[i];
+                const int head = S.sst->qhead;
+                for (int k = 1; k < m; k++) {
+                    const int slot = (head - (k - 1) + NHIST) % NHIST;
+                    q0 += pred_coef(m, k) * S.q_ring[(size_t)slot * S.n + i];
+                }
+            }
         }
         S.q[s] = q0;
     } else if (s < S.npad) {

@@ -679,15 +679,22 @@ __global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *seg
     const Seg &S = segs[T.seg];
     if (gate && (!S.sst->done || S.sst->forces_done)) return;
     __shared__ V4 dtab[NCODE];
-    __shared__ double lds[4];
+    __shared__ double lds[4 * 3];
     load_dtab2<R>(S, dtab);
     const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
     const auto qv = gbl(S.q);
     const double qsh = S.sst->qshift;
-    const bool keep_hist = S.q_h1 != nullptr;
+    const bool keep_hist = S.q_ring != nullptr;
+    const int push = (S.sst->qhead + 1) % NHIST;       // ring slot that takes the previous solution
     constexpr int G = TILE / LPR;
     const int lane = threadIdx.x % LPR;
     double esum = 0.0;
+    // bond statistics of the step (for the measurement): bonds and ordered bond pairs
+    double nb = 0.0, nt = 0.0;
+    if (T.row0 + (int)threadIdx.x < S.n) {
+        nb = (double)S.bcnt[T.row0 + threadIdx.x];
+        nt = nb * (nb - 1.0);
+    }
     for (int k = threadIdx.x / LPR; k < TILE; k += G) {
         const int s = T.row0 + k;
         if (s >= S.n) continue;
@@ -731,32 +738,31 @@ __global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *seg
             S.F[S.n + i] = qs * fy + S.Fcov[S.npad + s];
             S.F[2 * S.n + i] = qs * fz + S.Fcov[2 * S.npad + s];
             S.q_out[i] = qs;
-            if (keep_hist) {
-                S.q_h3[i] = S.q_h2[i];
-                S.q_h2[i] = S.q_h1[i];
-                S.q_h1[i] = S.q_state[i];
-            }
+            if (keep_hist) S.q_ring[(size_t)push * S.n + i] = S.q_state[i];
             S.q_state[i] = qs;
             esum += PD.E0[ti] + PD.chi[ti] * qs + 0.5 * PD.J[ti] * qs * qs + 0.5 * qs * ec + S.ecov[s];
         }
     }
-    double v[1] = {esum};
-    tile_partials<1>(S, T.row0 / TILE, v, lds);
+    double v[3] = {esum, nb, nt};
+    tile_partials<3>(S, T.row0 / TILE, v, lds);
 }
 
 __global__ void k_fin_energy(const int *seg_ids, Seg *segs, int gate)
 {
     const Seg &S = segs[seg_ids[blockIdx.x]];
     if (gate && (!S.sst->done || S.sst->forces_done)) return;
-    __shared__ double lds[4];
-    double tot[1];
-    seg_total<1>(S, lds, tot);
+    __shared__ double lds[4 * 3];
+    double tot[3];
+    seg_total<3>(S, lds, tot);
     if (threadIdx.x == 0) {
         SegState *st = S.sst;
         st->energy = tot[0];
+        st->nbond = tot[1];
+        st->ntrip = tot[2];
         if (S.E_out) *S.E_out = tot[0];
         st->mu_prev = st->mshift;
-        st->nhist = st->nhist < 4 ? st->nhist + 1 : 4;
+        st->nhist = st->nhist < NHIST + 1 ? st->nhist + 1 : NHIST + 1;
+        if (S.q_ring) st->qhead = (st->qhead + 1) % NHIST;
         st->forces_done = 1;
     }
 }
