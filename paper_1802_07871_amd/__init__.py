@@ -129,13 +129,20 @@ class System:
     """Caller-owned device buffer that carries one atomic system's lists,
     sort order and warm-start charges between calls."""
 
-    def __init__(self, pot: "Potential", n: int, box, pbc):
+    def __init__(self, pot: "Potential", n: int, box, pbc, buf=None):
+        """buf: optional uint8 CUDA tensor of at least the system's bytes to
+        use instead of a new allocation (it is reset for this system)."""
         torch = _torch()
         b, p = _box_pbc(box, pbc)
         nbytes = ctypes.c_size_t()
         _check(lib().ctbop_system_bytes(pot.ctx, int(n), b.ctypes.data, p.ctypes.data, ctypes.byref(nbytes)))
         self.nbytes = int(nbytes.value)
-        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device="cuda")
+        if buf is None:
+            self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device="cuda")
+        else:
+            if buf.dtype != torch.uint8 or not buf.is_cuda or buf.numel() < self.nbytes:
+                raise ValueError(f"buffer must be a uint8 CUDA tensor of at least {self.nbytes} bytes")
+            self.buf = buf
         self.n = int(n)
         # the allocator may hand out the address of a freed buffer again: the
         # context must not take this memory's contents for a system it knows
@@ -171,8 +178,14 @@ class Potential:
         except Exception:
             pass
 
-    def system(self, n, box, pbc) -> System:
-        return System(self, n, box, pbc)
+    def system(self, n, box, pbc, buf=None) -> System:
+        return System(self, n, box, pbc, buf=buf)
+
+    def system_bytes(self, n, box, pbc) -> int:
+        b, p = _box_pbc(box, pbc)
+        nbytes = ctypes.c_size_t()
+        _check(lib().ctbop_system_bytes(self.ctx, int(n), b.ctypes.data, p.ctypes.data, ctypes.byref(nbytes)))
+        return int(nbytes.value)
 
     def set_params(self, params):
         """Replace the parameters in place (every system buffer starts over)."""
@@ -239,14 +252,15 @@ class Potential:
         _check(rc)
         return E, F, q, (info.as_dict() if info is not None else None)
 
-    def compute(self, pos, types, box, pbc, Q=0.0, warm=True, force_rebuild=False, sysbuf=None):
+    def compute(self, pos, types, box, pbc, Q=0.0, warm=True, force_rebuild=False, sysbuf=None, want_info=True):
         """pos (n,3) and types (n,) as numpy arrays or tensors.  Returns
-        (E float, F (n,3) float64 tensor, q (n,) tensor, info dict)."""
+        (E float, F (n,3) float64 tensor, q (n,) tensor, info dict or None)."""
         torch = _torch()
         pos = torch.as_tensor(pos, dtype=torch.float64, device="cuda").reshape(-1, 3)
         types = torch.as_tensor(types, dtype=torch.int32, device="cuda").contiguous()
         pos_soa = pos.t().contiguous().reshape(-1)
-        E, F, q, info = self.compute_soa(pos_soa, types, box, pbc, Q, warm, force_rebuild, sysbuf)
+        E, F, q, info = self.compute_soa(pos_soa, types, box, pbc, Q, warm, force_rebuild, sysbuf,
+                                         want_info=want_info)
         n = types.shape[0]
         return float(E.item()), F.reshape(3, n).t().contiguous(), q, info
 
