@@ -139,13 +139,17 @@ typedef struct {
     double cg_res0;     /* starting RMS projected residual of the last solve   */
     unsigned long long nnz_coul;  /* Coulomb entries inside rc at the last assembly */
     unsigned long long nnz_coul_wide; /* of which stored with full (32-bit) indices in the
-                                         solver's sliced copy (the rest: 16-bit offsets) */
+                                         solver's sliced copy (the rest: 16-bit halo
+                                         positions or offsets)                         */
     unsigned long long nnz_coul_slots; /* entry slots the solver's product reads: per
                                           slice of 64 rows, 64 x its longest row */
     unsigned long long n_bonds;        /* covalent bonds (ordered pairs inside S_ij) at the
                                           last evaluation                              */
     unsigned long long n_triplets;     /* ordered bond pairs (i; j, k), j != k, sharing
                                           the centre i: the zeta_l terms (Eq. 2)        */
+    unsigned long long nnz_coul_halo;  /* Coulomb entries whose tile stages the charge
+                                          direction of its neighbours in on-chip memory
+                                          (16-bit halo positions) at the last assembly  */
 } ctbop_info;
 
 /* Fill *o with the defaults above. */

@@ -47,7 +47,7 @@ class Info(ctypes.Structure):
                 ("cg_iters_total", ctypes.c_ulonglong), ("cg_res0", ctypes.c_double),
                 ("nnz_coul", ctypes.c_ulonglong), ("nnz_coul_wide", ctypes.c_ulonglong),
                 ("nnz_coul_slots", ctypes.c_ulonglong), ("n_bonds", ctypes.c_ulonglong),
-                ("n_triplets", ctypes.c_ulonglong)]
+                ("n_triplets", ctypes.c_ulonglong), ("nnz_coul_halo", ctypes.c_ulonglong)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -226,6 +226,9 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
     size_t o_hcnt = take(4 * np), o_hidx = take(4 * np * S.Wl), o_Hr = take(rsz * np * S.Wl);
     size_t o_hsidx = take(4 * np * S.Wl), o_hs16 = take(2 * np * S.Wl), o_hwide = take(np), o_swide = take(np / SLICE);
     size_t o_hperm = take(np);
+    const size_t nt = (size_t)S.ntile;
+    size_t o_halo = take(4 * nt * HALO_MAX), o_nhalo = take(4 * nt), o_hbits = take(8 * nt * HALO_WORDS),
+           o_hpre = take(2 * nt * HALO_WORDS);
     size_t o_scnt = take(4 * np), o_sidx = take(4 * np * S.Ws), o_srev = take(np * S.Ws);
     size_t o_bcnt = take(4 * np), o_bidx = take(4 * np * S.Wb), o_bsrev = take(np * S.Wb), o_cmap = take(np * S.Ws),
            o_slot = take(v4 * np * S.Wb);
@@ -265,6 +268,10 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
         S.hwide = (uint8_t *)(base + o_hwide);
         S.swide = (uint8_t *)(base + o_swide);
         S.hperm = (uint8_t *)(base + o_hperm);
+        S.halo = (uint32_t *)(base + o_halo);
+        S.nhalo = (int *)(base + o_nhalo);
+        S.hbits = (unsigned long long *)(base + o_hbits);
+        S.hpre = (uint16_t *)(base + o_hpre);
         S.scnt = (int *)(base + o_scnt);
         S.sidx = (uint32_t *)(base + o_sidx);
         S.srev = (uint8_t *)(base + o_srev);
@@ -653,6 +660,7 @@ int fill_info(ctbop_ctx *ctx, Prep &P, ctbop_info *info)
     info->nnz_coul = (unsigned long long)ss.nnz_coul;
     info->nnz_coul_wide = (unsigned long long)ss.nnz_wide;
     info->nnz_coul_slots = (unsigned long long)ss.nnz_slots;
+    info->nnz_coul_halo = (unsigned long long)ss.nnz_halo;
     info->n_bonds = (unsigned long long)ss.nbond;
     info->n_triplets = (unsigned long long)ss.ntrip;
     if (ss.status) return fail(info->status, status_text(ss.status));

@@ -26,6 +26,14 @@ constexpr int BK = 16;                 // rows per block of the block-Jacobi pre
 constexpr int WB = 32;                 // bond-row capacity (bonds inside S_ij per atom)
 constexpr int NHIST = 3;               // charge solutions kept before the latest (predictor history)
 constexpr int PRED_ORDER = 4;          // points of the starting-charge extrapolation (1..NHIST+1)
+constexpr int HALO_WIN = 65536;        // rows around a tile's first row whose charges a tile may stage
+constexpr int HALO_WORDS = HALO_WIN / 64;
+#ifndef CTBOP_HALO_MAX
+#define CTBOP_HALO_MAX 3072
+#endif
+constexpr int HALO_MAX = CTBOP_HALO_MAX; // staged rows per tile in the charge-solve product (LDS doubles)
+// forms of a slice of the solver's sliced copy (swide)
+constexpr uint8_t SL_HALO = 0, SL_FULL = 1, SL_OFF16 = 2;
 
 // status bits (mapped to CTBOP_E_* codes on the host)
 constexpr int ST_TOO_CLOSE = 1, ST_NOCONV = 2, ST_NOT_PD = 4, ST_OVERFLOW = 8, ST_REV = 16;
@@ -80,6 +88,7 @@ struct SegState {
     double res0;                              // starting residual of the last solve
     double nnz_coul;                          // Coulomb entries inside rc at the last assembly
     double nnz_wide;                          // of which in slices that keep full entries
+    double nnz_halo;                          // of which in slices of halo positions
     double nnz_slots;                         // entry slots the sliced product reads: 64 x longest row, per slice
     double nbond, ntrip;                      // bonds and ordered bond pairs (i; j, k) at the last evaluation
     // charge coupling (f_q) solve: p^T r, p^T H p and the coupling part of
@@ -132,19 +141,33 @@ struct Seg {
     int *hcnt;         // [npad]
     uint32_t *hidx;    // [npad * Wl]
     void *Hr;          // [npad * Wl] float / double
-    // In the sliced copy the neighbour row is stored as a 16-bit offset from
-    // the slice's first row (hs16, offset + 32768) when every entry of the
-    // slice lies within that window (swide = 0), else as the full entry
-    // (hsidx); hwide flags the rows that need the full form wherever in its
-    // tile the row is placed.  Within each tile the rows take the slice
-    // slots in order of decreasing length (ties by row), so that the rows of
-    // a slice have similar lengths and a wave reads few padding slots; slot t
-    // of a tile holds row hperm[t] of that tile.
+    // The halo of a tile is the sorted set of distinct rows of its rows'
+    // list entries (r < rc + skin at the last build) that lie within
+    // HALO_WIN / 2 rows of the tile's first row: the list build marks them
+    // in a bitmap over that window (hbits), with the running count of set
+    // bits before each 64-bit word (hpre); halo lists them, nhalo counts
+    // them.  The charge-solve product stages p of the halo in LDS once per
+    // tile, so that each entry gathers from LDS.  In the sliced copy the
+    // neighbours of a slice's entries are stored in one of three forms
+    // (swide): their 16-bit positions in the tile's halo (hs16, SL_HALO)
+    // when the halo holds at most HALO_MAX rows, else 16-bit offsets from
+    // the slice's first slot (hs16, offset + 32768, SL_OFF16), and the full
+    // entries (hsidx, SL_FULL) when a row of the slice has an entry beyond a
+    // 16-bit offset from some slice of its tile (hwide flags those rows;
+    // the entries of the other rows lie in the halo window).  Within each
+    // tile the rows take the slice slots in order of decreasing length (ties
+    // by row), so that the rows of a slice have similar lengths and a wave
+    // reads few padding slots; slot t of a tile holds row hperm[t] of that
+    // tile.
     uint32_t *hsidx;   // [npad * Wl]
     uint16_t *hs16;    // [npad * Wl]
     uint8_t *hwide;    // [npad]
     uint8_t *swide;    // [npad / SLICE], per slice of slots
     uint8_t *hperm;    // [npad]
+    uint32_t *halo;    // [ntile * HALO_MAX]
+    int *nhalo;        // [ntile]
+    unsigned long long *hbits;  // [ntile * HALO_WORDS]
+    uint16_t *hpre;    // [ntile * HALO_WORDS]
     void *H;           // [npad * Wl] float / double
     // covalent list: r < S_ij + skin at the last build, row-major, stride Ws
     int *scnt;         // [npad]

@@ -127,9 +127,9 @@ __global__ void __launch_bounds__(TILE) k_adj_init(const Tile *tiles, Seg *segs,
 {
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
-    __shared__ double lds[4 * 5];
+    __shared__ double lds[4 * 6];
     const int s = T.row0 + threadIdx.x;
-    double v[5] = {0, 0, 0, 0, 0};
+    double v[6] = {0, 0, 0, 0, 0, 0};
     if (s < S.n) {
         const double r = A.a[s];
         S.q[s] = 0.0;          // the adjoint view's q is lambda
@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(TILE) k_adj_init(const Tile *tiles, Seg *segs,
     } else if (s < S.npad) {
         S.q[s] = 0.0;
     }
-    tile_partials<5>(S, T.row0 / TILE, v, lds);
+    tile_partials<6>(S, T.row0 / TILE, v, lds);
 }
 
 __global__ void k_adj_keep_lam_shift(const int *seg_ids, Seg *segs, AdjWs A)

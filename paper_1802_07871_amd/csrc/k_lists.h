@@ -278,6 +278,58 @@ __device__ __forceinline__ void load_dtab(const Seg &S, typename Vec4<R>::type *
     __syncthreads();
 }
 
+// The tile's halo from its bitmap (in LDS, HALO_WORDS words, complete): the
+// distinct rows of its list entries within HALO_WIN / 2 rows of its first
+// row.  hpre holds the set bits before each word, halo the marked rows in
+// order (when at most HALO_MAX), nhalo their number.  Every thread of the
+// block calls it.
+__device__ __forceinline__ void write_halo(const Seg &S, const Tile &T, const unsigned long long *bm, int *wsum)
+{
+    constexpr int WPT = HALO_WORDS / TILE;   // words per thread
+    static_assert(HALO_WORDS % TILE == 0, "whole words per thread");
+    const int tl = T.row0 / TILE;
+    const int w0 = threadIdx.x * WPT;
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < WPT; k++) c += __popcll(bm[w0 + k]);
+    // exclusive scan of c over the block: within the wave, then the waves
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int inc = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    int before = inc - c, total = 0;
+    for (int w = 0; w < TILE / 64; w++) {
+        if (w < wv) before += wsum[w];
+        total += wsum[w];
+    }
+    const auto hb = gblw(S.hbits + (size_t)tl * HALO_WORDS);
+    const auto hp = gblw(S.hpre + (size_t)tl * HALO_WORDS);
+    const auto hl = gblw(S.halo + (size_t)tl * HALO_MAX);
+    const int org = T.row0 - HALO_WIN / 2;
+    int at = before;
+#pragma unroll
+    for (int k = 0; k < WPT; k++) {
+        unsigned long long b = bm[w0 + k];
+        hb[w0 + k] = b;
+        hp[w0 + k] = (uint16_t)at;
+        if (total <= HALO_MAX) {
+            while (b) {
+                const int bit = __ffsll((long long)b) - 1;
+                hl[at++] = (uint32_t)(org + 64 * (w0 + k) + bit);
+                b &= b - 1;
+            }
+        } else {
+            at += __popcll(b);
+        }
+    }
+    if (threadIdx.x == 0) S.nhalo[tl] = total;
+}
+
 // Both lists for every sorted atom: the cell stencil visited in a fixed order,
 // each cell's atoms in sorted order, so rows are deterministic.  L lanes per
 // atom take L consecutive atoms of a cell at a time (one coalesced read of
@@ -292,7 +344,11 @@ __global__ void __launch_bounds__(TILE) k_build(const Tile *tiles, Seg *segs, Pa
     if (!S.sst->rebuild) return;
     __shared__ V4 dtab[NCODE];
     __shared__ int red[4][5];
+    __shared__ unsigned long long hbm[HALO_WORDS];
+    __shared__ int wsum[TILE / 64];
+    for (int w = threadIdx.x; w < HALO_WORDS; w += TILE) hbm[w] = 0ull;
     load_dtab<R>(S, dtab);
+    __syncthreads();
     const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
     // the segment's fields in registers: the list stores below cannot change them
     const int Wl = S.Wl, Ws = S.Ws, n = S.n;
@@ -363,6 +419,8 @@ __global__ void __launch_bounds__(TILE) k_build(const Tile *tiles, Seg *segs, Pa
                         if (inl) {
                             const int at = nl + __popc(gl & below);
                             if (at < Wl) lrow[at] = ent;
+                            const int hw = m - T.row0 + HALO_WIN / 2;
+                            if ((unsigned)hw < (unsigned)HALO_WIN) atomicOr(&hbm[hw >> 6], 1ull << (hw & 63));
                         }
                         if (ins) {
                             const int at = ns + __popc(gs & below);
@@ -420,6 +478,7 @@ __global__ void __launch_bounds__(TILE) k_build(const Tile *tiles, Seg *segs, Pa
         atomicAdd(&S.sst->nnz_long, (unsigned long long)red[0][3]);
         atomicAdd(&S.sst->nnz_short, (unsigned long long)red[0][4]);
     }
+    write_halo(S, T, hbm, wsum);
 }
 
 // For every covalent entry (i -> j, d) the slot of (j -> i, -d) in row j.

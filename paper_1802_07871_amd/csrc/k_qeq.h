@@ -93,7 +93,9 @@ __device__ __forceinline__ double entry_r(const typename Vec4<R>::type &li, cons
 
 // Assemble the Coulomb rows of the step: the list entries inside rc, in list
 // order, into hidx/Hr (group ballots give each lane its place), and the
-// starting residual r = -(H q0 + chi) + mu_prev.
+// starting residual r = -(H q0 + chi) + mu_prev.  A row is flagged (hwide)
+// when one of its entries lies further from the tile than a 16-bit offset
+// from any slice of the tile reaches (which keeps it in the halo window too).
 template <typename R, int LPR>
 __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs, Params<double> PD)
 {
@@ -256,13 +258,24 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
     __shared__ int slot_cnt[TILE];
     __shared__ uint8_t wide_row[TILE];
     __shared__ uint8_t sw[TILE / SLICE];
-    __shared__ double lds[4 * 5];
+    __shared__ double lds[4 * 6];
+    __shared__ unsigned long long hbm[HALO_WORDS];
+    __shared__ uint16_t hpre[HALO_WORDS];
     const int tid = threadIdx.x;
     const int own = T.row0 + tid;
     const bool live = own < S.n;
     const int own_cnt = live ? S.hcnt[own] : 0;
     cnt_lds[tid] = own_cnt;
     wide_row[tid] = (live && S.hwide[own] != 0) ? 1 : 0;
+    // the tile's halo bitmap: an entry's place in the halo is the set bits before its own
+    const int tl = T.row0 / TILE;
+    const bool hfit = S.nhalo[tl] <= HALO_MAX;
+    if (hfit) {
+        for (int w = tid; w < HALO_WORDS; w += TILE) {
+            hbm[w] = S.hbits[(size_t)tl * HALO_WORDS + w];
+            hpre[w] = S.hpre[(size_t)tl * HALO_WORDS + w];
+        }
+    }
     __syncthreads();
     // slot of each row: longer rows first, ties by row
     int rank = 0;
@@ -273,15 +286,16 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
     slot_row[rank] = tid;
     slot_cnt[rank] = own_cnt;
     __syncthreads();
-    // thread tid's slot is tid (row rk); a wave is a slice: the 16-bit form
-    // unless one of its rows needs the full one
+    // thread tid's slot is tid (row rk); a wave is a slice: the full form
+    // when one of its rows needs it, else halo positions when the halo fits,
+    // else 16-bit offsets from the slice's first slot
     const int rk = slot_row[tid];
     const int rrow = T.row0 + rk;
     S.hperm[own] = (uint8_t)rk;
-    const bool swide = __ballot(wide_row[rk] != 0) != 0ull;
+    const uint8_t smode = __ballot(wide_row[rk] != 0) != 0ull ? SL_FULL : (hfit ? SL_HALO : SL_OFF16);
     if ((tid & (SLICE - 1)) == 0) {
-        S.swide[own / SLICE] = swide ? 1 : 0;
-        sw[tid / SLICE] = swide ? 1 : 0;
+        S.swide[own / SLICE] = smode;
+        sw[tid / SLICE] = smode;
     }
     // slots padded to the slice's longest row (its first slot)
     const double slots = (tid & (SLICE - 1)) == 0 ? (double)SLICE * (double)slot_cnt[tid] : 0.0;
@@ -295,7 +309,7 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
         const int slot0 = sl * SLICE;
         const int sbase = T.row0 + slot0;
         const int mlen = slot_cnt[slot0];
-        const bool wide = sw[sl] != 0;
+        const int mode = sw[sl];
         // reading: lanes 4l .. 4l+3 take slot l's row
         const int rl = tid / HS_LPR, rq = tid % HS_LPR;
         const int rrk = slot_row[slot0 + rl];
@@ -335,8 +349,15 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
                 const int e = E0 + c;
                 if (e < wcnt) {
                     const uint32_t ent = ci[wl][c];
-                    if (wide) hsidx[b0 + (size_t)e * SLICE] = ent;
-                    else hs16[b0 + (size_t)e * SLICE] = (uint16_t)((int)(ent & J_MASK) - sbase + 32768);
+                    if (mode == SL_HALO) {
+                        const int hw = (int)(ent & J_MASK) - T.row0 + HALO_WIN / 2;
+                        const unsigned long long below = (1ull << (hw & 63)) - 1ull;
+                        hs16[b0 + (size_t)e * SLICE] = (uint16_t)(hpre[hw >> 6] + __popcll(hbm[hw >> 6] & below));
+                    } else if (mode == SL_OFF16) {
+                        hs16[b0 + (size_t)e * SLICE] = (uint16_t)((int)(ent & J_MASK) - sbase + 32768);
+                    } else {
+                        hsidx[b0 + (size_t)e * SLICE] = ent;
+                    }
                     H[b0 + (size_t)e * SLICE] = cv[wl][c];
                 }
             }
@@ -394,18 +415,19 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
         bo[t * BK + i] = b;
         m1 += (double)b;
     }
-    double v[5] = {0, 0, 0, 0, 0};
+    double v[6] = {0, 0, 0, 0, 0, 0};
     if (live) {
         S.m1[own] = m1;
         v[0] = S.r[own] * m1;
         v[1] = (double)own_cnt;
-        v[2] = sw[rank / SLICE] ? (double)own_cnt : 0.0;
+        v[2] = sw[rank / SLICE] == SL_FULL ? (double)own_cnt : 0.0;
         v[4] = m1;
+        v[5] = sw[rank / SLICE] == SL_HALO ? (double)own_cnt : 0.0;
     } else if (own < S.npad) {
         S.m1[own] = 0.0;
     }
     v[3] = slots;
-    tile_partials<5>(S, T.row0 / TILE, v, lds);
+    tile_partials<6>(S, T.row0 / TILE, v, lds);
 }
 
 // y = M r for row s: the row of s's block inverse against the block's r,
@@ -424,9 +446,9 @@ __device__ __forceinline__ double block_apply(const float *binv, int s, double r
 __global__ void k_fin_w0(const int *seg_ids, Seg *segs)
 {
     const Seg &S = segs[seg_ids[blockIdx.x]];
-    __shared__ double lds[4 * 5];
-    double tot[5];
-    seg_total<5>(S, lds, tot);
+    __shared__ double lds[4 * 6];
+    double tot[6];
+    seg_total<6>(S, lds, tot);
     if (threadIdx.x == 0) {
         SegState *st = S.sst;
         st->sdinv = tot[4];
@@ -434,6 +456,7 @@ __global__ void k_fin_w0(const int *seg_ids, Seg *segs)
         st->nnz_coul = tot[1];
         st->nnz_wide = tot[2];
         st->nnz_slots = tot[3];
+        st->nnz_halo = tot[5];
     }
 }
 
@@ -546,11 +569,43 @@ __device__ __forceinline__ double spmv_row(const double *p_, const IDX *row_, co
     return a;
 }
 
+// The same with p of the tile's halo staged in LDS (hp) and the row's
+// entries as 16-bit halo positions; products and sums in the same order.
+template <typename R, int U>
+__device__ __forceinline__ double spmv_row_halo(const double *hp, const uint16_t *row_, const R *hrow_, int cnt)
+{
+    const auto row = gbl(row_);
+    const auto hrow = gbl(hrow_);
+    double acc[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) acc[u] = 0.0;
+    int e = 0;
+    for (; e + U <= cnt; e += U) {
+        uint16_t jj[U];
+        R hh[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            jj[u] = __builtin_nontemporal_load(row + (size_t)(e + u) * SLICE);
+            hh[u] = __builtin_nontemporal_load(hrow + (size_t)(e + u) * SLICE);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) acc[u] += (double)hh[u] * hp[jj[u]];
+    }
+    for (; e < cnt; e++)
+        acc[0] += (double)__builtin_nontemporal_load(hrow + (size_t)e * SLICE) *
+                  hp[__builtin_nontemporal_load(row + (size_t)e * SLICE)];
+    double a = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; u++) a += acc[u];
+    return a;
+}
+
 // s = H p and the tile's share of p^T s, one slot (row) per lane over the
 // sliced copy; U entries of the row are loaded before their products are
-// summed, so U gathers of p are in flight per lane (U accumulators, combined
-// in a fixed order at the end).  A slice reads 16-bit row offsets (6 bytes
-// per entry) unless it needs the full entries.
+// summed (U accumulators, combined in a fixed order at the end).  The block
+// first stages p of its tile's halo in LDS; a slice of halo positions then
+// reads 6 bytes per entry from memory and p from LDS.  Slices of 16-bit
+// offsets (the halo did not fit) or full entries gather p from memory.
 // With FQ (the f_q coupling's nonlinear solve) the tile's share of p^T r
 // comes along as a second partial, for the line search.
 template <typename R, int U, bool FQ = false>
@@ -560,6 +615,15 @@ __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
     const Seg &S = segs[T.seg];
     if (S.sst->done) return;
     __shared__ double lds[4 * 2];
+    __shared__ double hp[HALO_MAX];
+    const int tl = T.row0 / TILE;
+    const int nh = S.nhalo[tl];
+    if (nh <= HALO_MAX) {
+        const auto hl = gbl(S.halo + (size_t)tl * HALO_MAX);
+        const auto pg = gbl(S.p);
+        for (int k = threadIdx.x; k < nh; k += TILE) hp[k] = pg[hl[k]];
+    }
+    __syncthreads();
     const int slot = T.row0 + threadIdx.x;
     const int s = T.row0 + S.hperm[slot];
     double pap = 0.0, pr = 0.0;
@@ -567,9 +631,11 @@ __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
         const size_t b0 = slice_base(slot, S.Wl);
         const R *hrow = reinterpret_cast<const R *>(S.H) + b0;
         const int cnt = S.hcnt[s];
-        const double a = S.swide[slot / SLICE]
-                             ? spmv_row<R, U, uint32_t>(S.p, S.hsidx + b0, hrow, cnt, 0)
-                             : spmv_row<R, U, uint16_t>(S.p, S.hs16 + b0, hrow, cnt, (slot & ~(SLICE - 1)) - 32768);
+        const int mode = S.swide[slot / SLICE];
+        const double a = mode == SL_HALO   ? spmv_row_halo<R, U>(hp, S.hs16 + b0, hrow, cnt)
+                         : mode == SL_FULL ? spmv_row<R, U, uint32_t>(S.p, S.hsidx + b0, hrow, cnt, 0)
+                                           : spmv_row<R, U, uint16_t>(S.p, S.hs16 + b0, hrow, cnt,
+                                                                      (slot & ~(SLICE - 1)) - 32768);
         const double ps = S.p[s];
         const double y = S.jd[s] * ps + a;
         S.s[s] = y;

@@ -175,10 +175,12 @@ __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Par
     const Seg &S = segs[T.seg];
     __shared__ double4 dtab[NCODE];
     __shared__ Params<double> Pl;
-    // the first BOND_CACHE bonds of each thread's atom: vector, length,
-    // cutoff value and pair type, computed once for the triplet loop
+    // the first BOND_CACHE bonds of each thread's atom: vector, length and
+    // pair type, computed once for the triplet loop (the cutoff value is
+    // recomputed from the length: 1 below R, which most bonds are, so the
+    // block's LDS stays under a third of a CU's and three blocks fit)
     __shared__ double cbx[BOND_CACHE][TILE], cby[BOND_CACHE][TILE], cbz[BOND_CACHE][TILE];
-    __shared__ double cbr[BOND_CACHE][TILE], cbf[BOND_CACHE][TILE];
+    __shared__ double cbr[BOND_CACHE][TILE];
     __shared__ uint8_t cbp[BOND_CACHE][TILE];
     stage_params(Pk, Pl);
     load_dtab2<double>(S, dtab);            // (ends with a barrier)
@@ -243,8 +245,9 @@ __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Par
             d.y = cby[e][threadIdx.x];
             d.z = cbz[e][threadIdx.x];
             r = cbr[e][threadIdx.x];
-            fcut = cbf[e][threadIdx.x];
             pp = cbp[e][threadIdx.x];
+            double dummy;
+            fcut = cutoff<double>(r, P.Rc[pp], P.Sc[pp], P.piSR[pp], dummy);
         } else {
             bond_geom(e, d, r, fcut, pp);
         }
@@ -258,7 +261,6 @@ __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Par
         cby[e][threadIdx.x] = d.y;
         cbz[e][threadIdx.x] = d.z;
         cbr[e][threadIdx.x] = r;
-        cbf[e][threadIdx.x] = fcut;
         cbp[e][threadIdx.x] = (uint8_t)pp;
     }
     double ecov = 0.0;
