@@ -429,7 +429,9 @@ size_t ctbop_server_table_bytes(int max_slots, int max_tiles);
 int ctbop_server_request_bytes(ctbop_ctx *ctx, int n, const double *box_host, const int *pbc_host, size_t *bytes);
 /* Start a server: arena_dev/arena_bytes caller-owned device memory, at most
  * max_slots requests in flight, cg_per_tick solver iterations per tick (0: 8;
- * four times as many in a tick that starts with no request waiting for admission),
+ * a tick that starts with no request waiting for admission iterates until its
+ * systems converge, checking between chunks, and ends early once a request
+ * arrives and cg_per_tick iterations have run),
  * all work on `stream` (its device is the current device). */
 int ctbop_server_create(ctbop_ctx *ctx, void *arena_dev, size_t arena_bytes, int max_slots, int cg_per_tick,
                         void *stream, ctbop_server **srv);

@@ -72,8 +72,14 @@ struct ctbop_server {
     size_t arena_bytes = 0;
     int max_slots = 0;
     int cg_per_tick = 8;
+    int iters_hint = 0;      // solver iterations of the last finished request (tick thread only)
     int device = 0;
     hipStream_t stream = nullptr;
+    // the covalent kernels of newly set-up systems run on a stream of the
+    // server's own beside the assembly and the solve, joined before the
+    // Coulomb forces (as the single-system path does)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // device tables at the head of the arena
     Seg *dsegs = nullptr;
     Tile *dtiles_setup = nullptr, *dtiles_act = nullptr;
@@ -247,8 +253,17 @@ int admit_one(ctbop_server *S, SrvReq &r, bool &placed)
     return CTBOP_OK;
 }
 
+// One tick: set up the newly admitted systems, run cg_iters solver
+// iterations over every active system, then the (gated) force kernels and
+// the harvest.  With poll set (nobody waiting for admission when the tick
+// began) the iterations go in chunks, the first as long as the last finished
+// request needed, then cg_check each, with a convergence check after each
+// chunk: the tick goes on until an active system has converged (or the
+// iteration limit), so that it is harvested at once, unless a request
+// arrives, which ends it at the next check once cg_iters have run.  A lone
+// request is then served in one tick, like a plain call.
 template <typename R>
-int server_tick(ctbop_server *S, const Params<R> &prm, int cg_iters)
+int server_tick(ctbop_server *S, const Params<R> &prm, int cg_iters, bool poll)
 {
     ctbop_ctx *ctx = S->ctx;
     hipStream_t st = S->stream;
@@ -300,7 +315,12 @@ int server_tick(ctbop_server *S, const Params<R> &prm, int cg_iters)
         hipLaunchKernelGGL((k_build<R, BUILD_L>), g, b, 0, st, T, S->dsegs, prm);
         hipLaunchKernelGGL(k_rev, g, b, 0, st, T, S->dsegs);
         hipLaunchKernelGGL(k_mark_built, dim3((nis + 63) / 64), dim3(64), 0, st, sid, S->dsegs, nis);
-        hipLaunchKernelGGL((k_bond<R>), g, b, 0, st, T, S->dsegs, ctx->pd);
+        // covalent energy and forces need only the lists: side stream
+        HIPCHK(hipEventRecord(S->ev_fork, st));
+        HIPCHK(hipStreamWaitEvent(S->side, S->ev_fork, 0));
+        hipLaunchKernelGGL((k_bond<R>), g, b, 0, S->side, T, S->dsegs, ctx->pd);
+        hipLaunchKernelGGL((k_force_cov<R>), g, b, 0, S->side, T, S->dsegs, prm, 0);
+        HIPCHK(hipEventRecord(S->ev_join, S->side));
         hipLaunchKernelGGL((k_assemble<R, LPR>), g, b, 0, st, T, S->dsegs, ctx->pd);
         hipLaunchKernelGGL((k_hslice<R>), g, b, 0, st, T, S->dsegs);
         CgCtl ctl{ctx->opts.cg_tol, ctx->opts.cg_maxit};
@@ -313,14 +333,32 @@ int server_tick(ctbop_server *S, const Params<R> &prm, int cg_iters)
         const int *sid = S->dids_act;
         Tile *T = S->dtiles_act;
         CgCtl ctl{ctx->opts.cg_tol, ctx->opts.cg_maxit};
-        for (int c = 0; c < cg_iters; c++) {
-            hipLaunchKernelGGL(k_cg_dir, g, b, 0, st, T, S->dsegs);
-            hipLaunchKernelGGL((k_spmv<R, SPMV_U>), g, b, 0, st, T, S->dsegs);
-            hipLaunchKernelGGL(k_fin_alpha, gs, b, 0, st, sid, S->dsegs);
-            hipLaunchKernelGGL(k_cg_update, g, b, 0, st, T, S->dsegs);
-            hipLaunchKernelGGL(k_fin_update, gs, b, 0, st, sid, S->dsegs, ctl);
+        const int limit = poll ? ctx->opts.cg_maxit + 1 : cg_iters;
+        for (int c = 0; c < limit;) {
+            const int first = std::max(ctx->opts.cg_check, std::min(S->iters_hint, ctx->opts.cg_maxit));
+            const int chunk = poll ? std::min(limit - c, c == 0 ? first : ctx->opts.cg_check) : cg_iters;
+            for (int k = 0; k < chunk; k++) {
+                hipLaunchKernelGGL(k_cg_dir, g, b, 0, st, T, S->dsegs);
+                hipLaunchKernelGGL((k_spmv<R, SPMV_U>), g, b, 0, st, T, S->dsegs);
+                hipLaunchKernelGGL(k_fin_alpha, gs, b, 0, st, sid, S->dsegs);
+                hipLaunchKernelGGL(k_cg_update, g, b, 0, st, T, S->dsegs);
+                hipLaunchKernelGGL(k_fin_update, gs, b, 0, st, sid, S->dsegs, ctl);
+            }
+            c += chunk;
+            if (!poll || c >= limit) break;
+            hipLaunchKernelGGL(k_collect, dim3((nia + 63) / 64), dim3(64), 0, st, sid, S->dsegs, nia, S->dflags);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(S->hflags, S->dflags, sizeof(int4) * nia, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            bool any_done = false;
+            for (int a = 0; a < nia; a++) any_done = any_done || S->hflags[a].x != 0;
+            if (any_done) break;
+            if (c >= cg_iters) {
+                std::lock_guard<std::mutex> lk(S->mu);
+                if (!S->pending.empty()) break;
+            }
         }
-        hipLaunchKernelGGL((k_force_cov<R>), g, b, 0, st, T, S->dsegs, prm, 1);
+        if (nts) HIPCHK(hipStreamWaitEvent(st, S->ev_join, 0));
         hipLaunchKernelGGL((k_force_coul<R, LPR>), g, b, 0, st, T, S->dsegs, ctx->pd, 1);
         hipLaunchKernelGGL(k_fin_energy, gs, b, 0, st, sid, S->dsegs, 1);
         hipLaunchKernelGGL(k_collect, dim3((nia + 63) / 64), dim3(64), 0, st, sid, S->dsegs, nia, S->dflags);
@@ -355,6 +393,7 @@ int server_tick(ctbop_server *S, const Params<R> &prm, int cg_iters)
         r.ticket = sl.req.ticket;
         r.status = map_status(S->hflags[a].z);
         r.cg_iters = S->hflags[a].w;
+        S->iters_hint = r.cg_iters;
         r.n_atoms = sl.req.n;
         r.t_submit = sl.req.t_submit;
         r.t_admit = sl.req.t_admit;
@@ -382,14 +421,30 @@ int server_tick(ctbop_server *S, const Params<R> &prm, int cg_iters)
     return CTBOP_OK;
 }
 
+// the server's stream, events and pinned tables (whichever exist)
+void release_handles(ctbop_server *S)
+{
+    if (S->side) {
+        (void)hipStreamSynchronize(S->side);
+        (void)hipStreamDestroy(S->side);
+    }
+    if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
+    if (S->ev_join) (void)hipEventDestroy(S->ev_join);
+    if (S->htiles) (void)hipHostFree(S->htiles);
+    if (S->hids) (void)hipHostFree(S->hids);
+    if (S->hflags) (void)hipHostFree(S->hflags);
+}
+
 void server_loop(ctbop_server *S)
 {
     (void)hipSetDevice(S->device);
     for (;;) {
         // solver iterations of this tick: with nobody waiting for admission,
-        // four times as many, so a lone request finishes in fewer ticks (each
-        // tick costs a host round trip and the gated force launches)
+        // iterate until the active systems converge (checked between chunks),
+        // so a lone request finishes in one tick (each tick costs table
+        // uploads, host round trips and the gated force launches)
         int cg_iters = S->cg_per_tick;
+        bool poll = false;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             bool any_active = false;
@@ -418,11 +473,11 @@ void server_loop(ctbop_server *S)
                 if (!placed) break;
                 S->pending.pop_front();
             }
-            if (S->pending.empty()) cg_iters = 4 * S->cg_per_tick;
+            if (S->pending.empty()) poll = true;
         }
         const double t0 = now_s();
-        int rc = S->ctx->opts.fp64 ? server_tick<double>(S, S->ctx->pd, cg_iters)
-                                   : server_tick<float>(S, S->ctx->pf, cg_iters);
+        int rc = S->ctx->opts.fp64 ? server_tick<double>(S, S->ctx->pd, cg_iters, poll)
+                                   : server_tick<float>(S, S->ctx->pf, cg_iters, poll);
         S->busy_s += now_s() - t0;
         if (rc) {
             std::lock_guard<std::mutex> lk(S->mu);
@@ -489,11 +544,15 @@ int ctbop_server_create(ctbop_ctx *ctx, void *arena, size_t arena_bytes, int max
     S->free_ranges[tb] = arena_bytes - tb;
     S->slots.resize(max_slots);
     if (hipGetDevice(&S->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming) != hipSuccess ||
         hipHostMalloc((void **)&S->htiles, sizeof(Tile) * 2 * S->max_tiles, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&S->hids, sizeof(int) * 2 * max_slots, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&S->hflags, sizeof(int4) * max_slots, hipHostMallocDefault) != hipSuccess) {
+        release_handles(S);
         delete S;
-        return fail(CTBOP_E_HIP, "pinned host tables");
+        return fail(CTBOP_E_HIP, "server stream, events or pinned host tables");
     }
     S->th = std::thread(server_loop, S);
     ctx->servers++;
@@ -575,9 +634,7 @@ int ctbop_server_destroy(ctbop_server *S)
     S->cv.notify_all();
     if (S->th.joinable()) S->th.join();
     (void)hipStreamSynchronize(S->stream);
-    if (S->htiles) (void)hipHostFree(S->htiles);
-    if (S->hids) (void)hipHostFree(S->hids);
-    if (S->hflags) (void)hipHostFree(S->hflags);
+    release_handles(S);
     S->ctx->servers--;
     delete S;
     return CTBOP_OK;
