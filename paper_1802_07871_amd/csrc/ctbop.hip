@@ -150,6 +150,49 @@ void fill_params(const double *t, const ctbop_opts &o, Params<R> &P)
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Geometry of the cell grid and the byte layout of the per-system buffer.
+// The list build's cell culling (Seg::cwi, Seg::cull2): the inverse of the
+// cell-grid matrix, and rl^2 over the smallest eigenvalue of its metric
+// (cyclic Jacobi rotations on the 3x3 symmetric matrix), widened by 1e-4
+// relative plus 1e-3 cell^2 for the FP32 arithmetic of the test.
+void cell_cull(Seg &S, double rl)
+{
+    const double(*c)[3] = S.cw;
+    const double det = c[0][0] * (c[1][1] * c[2][2] - c[1][2] * c[2][1]) -
+                       c[0][1] * (c[1][0] * c[2][2] - c[1][2] * c[2][0]) +
+                       c[0][2] * (c[1][0] * c[2][1] - c[1][1] * c[2][0]);
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            // (c^-1)[a][b] = cofactor(b, a) / det
+            const int r0 = (b + 1) % 3, r1 = (b + 2) % 3, q0 = (a + 1) % 3, q1 = (a + 2) % 3;
+            S.cwi[a][b] = (float)((c[r0][q0] * c[r1][q1] - c[r0][q1] * c[r1][q0]) / det);
+        }
+    double g[3][3];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) g[a][b] = c[a][0] * c[b][0] + c[a][1] * c[b][1] + c[a][2] * c[b][2];
+    for (int sweep = 0; sweep < 50; sweep++) {
+        const double off = g[0][1] * g[0][1] + g[0][2] * g[0][2] + g[1][2] * g[1][2];
+        if (off <= 1e-30 * (g[0][0] * g[0][0] + g[1][1] * g[1][1] + g[2][2] * g[2][2])) break;
+        for (int p = 0; p < 2; p++)
+            for (int q = p + 1; q < 3; q++) {
+                if (g[p][q] == 0.0) continue;
+                const double th = 0.5 * std::atan2(2.0 * g[p][q], g[q][q] - g[p][p]);
+                const double cs = std::cos(th), sn = std::sin(th);
+                for (int k = 0; k < 3; k++) {          // columns p, q
+                    const double gp = g[k][p], gq = g[k][q];
+                    g[k][p] = cs * gp - sn * gq;
+                    g[k][q] = sn * gp + cs * gq;
+                }
+                for (int k = 0; k < 3; k++) {          // rows p, q
+                    const double gp = g[p][k], gq = g[q][k];
+                    g[p][k] = cs * gp - sn * gq;
+                    g[q][k] = sn * gp + cs * gq;
+                }
+            }
+    }
+    const double lam = std::min(g[0][0], std::min(g[1][1], g[2][2]));
+    S.cull2 = (float)(rl * rl / lam * (1.0 + 1e-4) + 1e-3);
+}
+
 int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, char *base, Layout &L)
 {
     if (n <= 0 || n > MAX_ATOMS) return fail(CTBOP_E_INVAL, "atom count out of range");
@@ -195,6 +238,7 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
         S.st[a] = st;
         for (int b = 0; b < 3; b++) S.cw[a][b] = h[a][b] / S.nb[a];
     }
+    cell_cull(S, rl);
     S.ncell = S.nb[0] * S.nb[1] * S.nb[2];
     S.n = n;
     S.npad = (n + TILE - 1) / TILE * TILE;
@@ -218,7 +262,7 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
     L.off_tiles = take(sizeof(Tile) * S.ntile);
     L.off_segid = take(sizeof(int));
     L.off_ke = take(8 * sizeof(double));
-    size_t o_perm = take(4 * np), o_cellof = take(4 * (size_t)n), o_csort = take(4 * np);
+    size_t o_perm = take(4 * np), o_permt = take(4 * np), o_cellof = take(4 * (size_t)n), o_csort = take(4 * np);
     size_t o_cs = take(4 * ((size_t)S.ncell + 1)), o_cc = take(4 * (size_t)S.ncell);
     size_t o_off = take(8 * 3 * np), o_ref = take(8 * 3 * (size_t)n), o_xs = take(v4 * np);
     size_t o_xs64 = fp64 ? o_xs : take(32 * np);
@@ -249,6 +293,7 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
     L.ntile = S.ntile;
     if (base) {
         S.perm = (int *)(base + o_perm);
+        S.perm_tmp = (int *)(base + o_permt);
         S.cell_of = (int *)(base + o_cellof);
         S.csort = (int *)(base + o_csort);
         S.cell_start = (int *)(base + o_cs);
@@ -478,7 +523,9 @@ void launch_lists(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags)
     hipLaunchKernelGGL(k_check_disp, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_bin_clear, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_bin, g, b, 0, st, P.dtiles, P.dseg);
-    hipLaunchKernelGGL(k_scan, g1, b, 0, st, sid, P.dseg);
+    hipLaunchKernelGGL(k_scan_part, g, b, 0, st, P.dtiles, P.dseg);
+    hipLaunchKernelGGL(k_scan_mid, g1, b, 0, st, sid, P.dseg);
+    hipLaunchKernelGGL(k_scan_fin, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_scatter, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_cell_sort, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_gather<R>, g, b, 0, st, P.dtiles, P.dseg, warm);

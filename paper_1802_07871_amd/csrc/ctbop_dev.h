@@ -103,6 +103,13 @@ struct Seg {
     double h[3][3];    // cell vectors as rows
     double hi[3][3];   // inverse: frac = x . hi
     double cw[3][3];   // cell-grid vectors: h[d] / nb[d]
+    // the list build's cell culling: an atom's fractional place in its cell
+    // is f = l . cwi (l its local coordinates); a point at fractional offset
+    // s from it lies at least sqrt(lam |s|^2) away, lam the smallest
+    // eigenvalue of the cell metric cw cw^T, so cells with |s|^2 > cull2 =
+    // (rc + skin)^2 / lam (a margin added) hold no list entry of the atom
+    float cwi[3][3];
+    float cull2;
     int pbc[3];
     int nb[3];         // cell grid
     int st[3];         // stencil half-width per direction (<= 3)
@@ -120,6 +127,7 @@ struct Seg {
     double *E_out;     // 1
     // persistent arrays
     int *perm;         // sorted row -> user index        [npad]
+    int *perm_tmp;     // the scatter's order of each cell's atoms (list build only) [npad]
     int *cell_of;      // user index -> cell              [n]
     int *csort;        // sorted row -> cell              [npad]
     int *cell_start;   // [ncell + 1]

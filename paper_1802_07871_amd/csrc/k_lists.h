@@ -112,30 +112,74 @@ __global__ void k_bin(const Tile *tiles, Seg *segs)
     atomicAdd(&S.cell_cnt[ci], 1);
 }
 
-// exclusive scan of the cell counts (one block per segment); the counts are
-// zeroed for use as fill counters
-__global__ void k_scan(const int *seg_ids, Seg *segs)
+// Exclusive scan of the cell counts into cell_start, in three passes over
+// the segment's tiles (each tile takes a contiguous chunk of the cells), with
+// the counts zeroed for use as fill counters: the chunks' sums (the tiles'
+// partials), their exclusive scan (one block per segment), then each chunk's
+// starts from its tile's offset.  Integer counts, so any order is exact.
+__device__ __forceinline__ void scan_chunk(const Seg &S, int tl, int &c0, int &c1)
+{
+    const int ch = (S.ncell + S.ntile - 1) / S.ntile;
+    c0 = min(S.ncell, tl * ch);
+    c1 = min(S.ncell, c0 + ch);
+}
+
+__global__ void __launch_bounds__(TILE) k_scan_part(const Tile *tiles, Seg *segs)
+{
+    const Tile T = my_tile(tiles);
+    const Seg &S = segs[T.seg];
+    if (!S.sst->rebuild) return;
+    __shared__ double lds[4];
+    int c0, c1;
+    scan_chunk(S, T.row0 / TILE, c0, c1);
+    double v[1] = {0.0};
+    for (int c = c0 + threadIdx.x; c < c1; c += TILE) v[0] += (double)S.cell_cnt[c];
+    tile_partials<1>(S, T.row0 / TILE, v, lds);
+}
+
+__global__ void __launch_bounds__(TILE) k_scan_mid(const int *seg_ids, Seg *segs)
 {
     const Seg &S = segs[seg_ids[blockIdx.x]];
     if (!S.sst->rebuild) return;
     __shared__ int lds[4];
-    // each thread scans one contiguous run of cells: its run's total, the
-    // block's exclusive scan of the totals, then the run's starts
-    const int per = (S.ncell + TILE - 1) / TILE;
-    const int c0 = min(S.ncell, (int)threadIdx.x * per), c1 = min(S.ncell, c0 + per);
+    // each thread a contiguous run of tiles: its run's total, the block's
+    // exclusive scan of the totals, then the run's offsets (in place)
+    const int per = (S.ntile + TILE - 1) / TILE;
+    const int t0 = min(S.ntile, (int)threadIdx.x * per), t1 = min(S.ntile, t0 + per);
     int sum = 0;
-#pragma unroll 16
-    for (int c = c0; c < c1; c++) sum += S.cell_cnt[c];
+    for (int t = t0; t < t1; t++) sum += (int)S.part[t];
     int run = block_excl_scan(sum, lds);
-#pragma unroll 16
-    for (int c = c0; c < c1; c++) {
-        const int v = S.cell_cnt[c];
-        S.cell_start[c] = run;
-        S.cell_cnt[c] = 0;
+    for (int t = t0; t < t1; t++) {
+        const int v = (int)S.part[t];
+        S.part[t] = (double)run;
         run += v;
     }
-    // the last thread's run ends at the total (trailing runs may be empty)
     if (threadIdx.x == TILE - 1) S.cell_start[S.ncell] = run;
+}
+
+__global__ void __launch_bounds__(TILE) k_scan_fin(const Tile *tiles, Seg *segs)
+{
+    const Tile T = my_tile(tiles);
+    const Seg &S = segs[T.seg];
+    if (!S.sst->rebuild) return;
+    __shared__ int lds[4];
+    __shared__ int tot;
+    int c0, c1;
+    scan_chunk(S, T.row0 / TILE, c0, c1);
+    int base = (int)S.part[T.row0 / TILE];
+    for (int cb = c0; cb < c1; cb += TILE) {
+        const int c = cb + threadIdx.x;
+        const int v = c < c1 ? S.cell_cnt[c] : 0;
+        const int ex = block_excl_scan(v, lds);
+        if (threadIdx.x == TILE - 1) tot = ex + v;
+        if (c < c1) {
+            S.cell_start[c] = base + ex;
+            S.cell_cnt[c] = 0;
+        }
+        __syncthreads();
+        base += tot;
+        __syncthreads();
+    }
 }
 
 __global__ void k_scatter(const Tile *tiles, Seg *segs)
@@ -147,44 +191,42 @@ __global__ void k_scatter(const Tile *tiles, Seg *segs)
     if (i >= S.n) return;
     int c = S.cell_of[i];
     int slot = S.cell_start[c] + atomicAdd(&S.cell_cnt[c], 1);
-    S.perm[slot] = i;
+    S.perm_tmp[slot] = i;
 }
 
 // Order each cell's atoms by user index (the scatter's order is arbitrary),
-// so the sorted frame -- and every sum over it -- is deterministic.  Then
-// record, per sorted row, its cell, its offset (fold minus cell origin) and
-// the reference positions for the displacement test.
+// so the sorted frame -- and every sum over it -- is deterministic: the atom
+// the scatter put at row k goes to its cell's first row plus the number of
+// the cell's atoms with a smaller user index.  Then record, per sorted row,
+// its cell, its offset (fold minus cell origin) and the reference positions
+// for the displacement test.
 __global__ void k_cell_sort(const Tile *tiles, Seg *segs)
 {
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     if (!S.sst->rebuild) return;
-    const int tl = T.row0 / TILE;
-    for (int c = tl * TILE + threadIdx.x; c < S.ncell; c += S.ntile * TILE) {
-        const int a = S.cell_start[c], b = S.cell_start[c + 1];
-        for (int k = a + 1; k < b; k++) {              // insertion sort, cells hold few atoms
-            int v = S.perm[k], m = k - 1;
-            while (m >= a && S.perm[m] > v) { S.perm[m + 1] = S.perm[m]; m--; }
-            S.perm[m + 1] = v;
-        }
-        const int c0 = c / (S.nb[1] * S.nb[2]), c1 = (c / S.nb[2]) % S.nb[1], c2 = c % S.nb[2];
-        for (int k = a; k < b; k++) {
-            const int i = S.perm[k];
-            const double x = S.x[i], y = S.x[S.n + i], z = S.x[2 * S.n + i];
-            double s[3], w[3];
-            frac_wrap(S, x, y, z, s, w);
-            S.csort[k] = c;
+    const int k = T.row0 + threadIdx.x;
+    if (k >= S.n) return;
+    const int i = S.perm_tmp[k];
+    const int c = S.cell_of[i];
+    const int a = S.cell_start[c], b = S.cell_start[c + 1];
+    int row = a;
+    for (int m = a; m < b; m++) row += (S.perm_tmp[m] < i) ? 1 : 0;
+    S.perm[row] = i;
+    const int c0 = c / (S.nb[1] * S.nb[2]), c1 = (c / S.nb[2]) % S.nb[1], c2 = c % S.nb[2];
+    const double x = S.x[i], y = S.x[S.n + i], z = S.x[2 * S.n + i];
+    double s[3], w[3];
+    frac_wrap(S, x, y, z, s, w);
+    S.csort[row] = c;
 #pragma unroll
-            for (int a2 = 0; a2 < 3; a2++) {
-                double o = w[0] * S.h[0][a2] + w[1] * S.h[1][a2] + w[2] * S.h[2][a2]
-                         - (c0 * S.cw[0][a2] + c1 * S.cw[1][a2] + c2 * S.cw[2][a2]);
-                S.off[a2 * S.npad + k] = o;
-            }
-            S.ref_x[i] = x;
-            S.ref_x[S.n + i] = y;
-            S.ref_x[2 * S.n + i] = z;
-        }
+    for (int a2 = 0; a2 < 3; a2++) {
+        double o = w[0] * S.h[0][a2] + w[1] * S.h[1][a2] + w[2] * S.h[2][a2]
+                 - (c0 * S.cw[0][a2] + c1 * S.cw[1][a2] + c2 * S.cw[2][a2]);
+        S.off[a2 * S.npad + row] = o;
     }
+    S.ref_x[i] = x;
+    S.ref_x[S.n + i] = y;
+    S.ref_x[2 * S.n + i] = z;
 }
 
 // Local coordinates of every sorted atom for this call's positions, and the
@@ -371,13 +413,30 @@ __global__ void __launch_bounds__(TILE) k_build(const Tile *tiles, Seg *segs, Pa
         const int c0 = c / (nb1 * nb2), c1 = (c / nb2) % nb1, c2 = c % nb2;
         const auto lrow = gblw(S.lidx + (size_t)s * Wl);
         const auto srow = gblw(S.sidx + (size_t)s * Ws);
+        // the atom's fractional place in its cell: a stencil cell at offset d
+        // spans fractional offsets [d - f, d - f + 1] from it per axis, at
+        // least g = max(0, d - f, f - d - 1) cells; cells whose g^2 sum
+        // exceeds cull2 hold no list entry and are not scanned (rows of the
+        // stencil whose first two g already do are skipped, and each row's
+        // run of cells along the last axis is trimmed to the sphere)
+        const float lx = (float)li.x, ly = (float)li.y, lz = (float)li.z;
+        const float f0 = lx * S.cwi[0][0] + ly * S.cwi[1][0] + lz * S.cwi[2][0];
+        const float f1 = lx * S.cwi[0][1] + ly * S.cwi[1][1] + lz * S.cwi[2][1];
+        const float f2 = lx * S.cwi[0][2] + ly * S.cwi[1][2] + lz * S.cwi[2][2];
+        const float cull2 = S.cull2;
         int nl = 0, ns = 0;
         bool close = false;
         for (int d0 = -st0; d0 <= st0; d0++) {
+            const float g0 = fmaxf(0.0f, fmaxf((float)d0 - f0, f0 - (float)d0 - 1.0f));
+            const float rem0 = cull2 - g0 * g0;
+            if (rem0 < 0.0f) continue;
             int e0 = c0 + d0;
             if (pbc0) { e0 %= nb0; if (e0 < 0) e0 += nb0; }
             else if (e0 < 0 || e0 >= nb0) continue;
             for (int d1 = -st1; d1 <= st1; d1++) {
+                const float g1 = fmaxf(0.0f, fmaxf((float)d1 - f1, f1 - (float)d1 - 1.0f));
+                const float rem1 = rem0 - g1 * g1;
+                if (rem1 < 0.0f) continue;
                 int e1 = c1 + d1;
                 if (pbc1) { e1 %= nb1; if (e1 < 0) e1 += nb1; }
                 else if (e1 < 0 || e1 >= nb1) continue;
@@ -387,7 +446,8 @@ __global__ void __launch_bounds__(TILE) k_build(const Tile *tiles, Seg *segs, Pa
                 // range (in the same order as cell by cell), and each lane
                 // takes its atom's offset from the atom's cell.
                 const int rowc = (e0 * nb1 + e1) * nb2;
-                int dlo = -st2, dhi = st2;
+                const float g2max = sqrtf(rem1);
+                int dlo = max(-st2, (int)ceilf(f2 - 1.0f - g2max)), dhi = min(st2, (int)floorf(f2 + g2max));
                 if (!pbc2) {
                     dlo = max(dlo, -c2);
                     dhi = min(dhi, nb2 - 1 - c2);

@@ -306,7 +306,9 @@ int server_tick(ctbop_server *S, const Params<R> &prm, int cg_iters, bool poll)
         hipLaunchKernelGGL(k_check_disp, g, b, 0, st, T, S->dsegs);
         hipLaunchKernelGGL(k_bin_clear, g, b, 0, st, T, S->dsegs);
         hipLaunchKernelGGL(k_bin, g, b, 0, st, T, S->dsegs);
-        hipLaunchKernelGGL(k_scan, gs, b, 0, st, sid, S->dsegs);
+        hipLaunchKernelGGL(k_scan_part, g, b, 0, st, T, S->dsegs);
+        hipLaunchKernelGGL(k_scan_mid, gs, b, 0, st, sid, S->dsegs);
+        hipLaunchKernelGGL(k_scan_fin, g, b, 0, st, T, S->dsegs);
         hipLaunchKernelGGL(k_scatter, g, b, 0, st, T, S->dsegs);
         hipLaunchKernelGGL(k_cell_sort, g, b, 0, st, T, S->dsegs);
         hipLaunchKernelGGL(k_gather<R>, g, b, 0, st, T, S->dsegs, -1);

@@ -19,6 +19,20 @@ pytestmark = pytest.mark.gpu
 TOL = {"mixed": dict(F=1e-5, E=1e-6, q=1e-6), "fp64": dict(F=1e-10, E=1e-10, q=1e-10)}
 
 
+def _sheared():
+    """3C-SiC 216 in a triclinic periodic cell: the cubic cell's vectors
+    replaced by integer combinations of them (the same lattice of images,
+    so the same crystal), a cell whose metric's smallest eigenvalue is well
+    below its squared widths, which the list build's cell culling uses to
+    bound distances."""
+    s = G.zincblende(3, sigma=0.05, seed=1003)
+    box = np.array(s.box, dtype=np.float64)
+    box[1] = box[1] + box[0]
+    box[2] = box[2] + box[0] - box[1]
+    s.box = box
+    return s
+
+
 def _cases():
     rng = np.random.Generator(np.random.PCG64(77))
     slab = G.slab_4h(6, 4, 6, step=True, seed=61)
@@ -30,6 +44,7 @@ def _cases():
         "periodic 1000": G.random_system(1000, 0.6, 3.0, True, seed=64),
         "stepped slab": slab,
         "graphene SW": G.graphene(8, 5, 2, seed=65),
+        "sheared 3C-SiC 216": _sheared(),
     }
 
 
