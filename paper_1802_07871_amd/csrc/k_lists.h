@@ -541,26 +541,34 @@ __global__ void __launch_bounds__(TILE) k_build(const Tile *tiles, Seg *segs, Pa
     write_halo(S, T, hbm, wsum);
 }
 
-// For every covalent entry (i -> j, d) the slot of (j -> i, -d) in row j.
-__global__ void k_rev(const Tile *tiles, Seg *segs)
+// For every covalent entry (i -> j, d) the slot of (j -> i, -d) in row j:
+// 16 lanes per row, one entry each, every lane searching its partner's row.
+__global__ void __launch_bounds__(TILE) k_rev(const Tile *tiles, Seg *segs)
 {
+    constexpr int LR = 16;
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     if (!S.sst->rebuild) return;
-    const int s = T.row0 + threadIdx.x;
-    if (s >= S.n) return;
-    const int ns = S.scnt[s];
-    int bad = 0;
-    for (int e = 0; e < ns; e++) {
-        const uint32_t ent = S.sidx[(size_t)s * S.Ws + e];
-        const int j = (int)(ent & J_MASK), want = code_neg((int)(ent >> CODE_SHIFT));
-        const uint32_t target = (uint32_t)s | ((uint32_t)want << CODE_SHIFT);
-        const int nj = S.scnt[j];
-        int f = -1;
-        for (int k = 0; k < nj; k++)
-            if (S.sidx[(size_t)j * S.Ws + k] == target) { f = k; break; }
-        if (f < 0) { bad = 1; f = 0; }
-        S.srev[(size_t)s * S.Ws + e] = (uint8_t)f;
+    const int lane = threadIdx.x % LR;
+    const int Ws = S.Ws;
+    const auto sidx = gbl(S.sidx);
+    const auto scnt = gbl(S.scnt);
+    bool bad = false;
+    for (int k = threadIdx.x / LR; k < TILE; k += TILE / LR) {
+        const int s = T.row0 + k;
+        if (s >= S.n) break;                     // rows past n come last: the group is done
+        const int ns = scnt[s];
+        for (int e = lane; e < ns; e += LR) {
+            const uint32_t ent = sidx[(size_t)s * Ws + e];
+            const int j = (int)(ent & J_MASK), want = code_neg((int)(ent >> CODE_SHIFT));
+            const uint32_t target = (uint32_t)s | ((uint32_t)want << CODE_SHIFT);
+            const int nj = scnt[j];
+            int f = -1;
+            for (int m = 0; m < nj; m++)
+                if (sidx[(size_t)j * Ws + m] == target) { f = m; break; }
+            if (f < 0) { bad = true; f = 0; }
+            S.srev[(size_t)s * Ws + e] = (uint8_t)f;
+        }
     }
     if (bad) atomicOr(&S.sst->status, ST_REV);
 }

@@ -329,10 +329,28 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
     // the first BOND_CACHE bonds of each thread's atom: vector, length, pair type
     __shared__ R cbx[BOND_CACHE][TILE], cby[BOND_CACHE][TILE], cbz[BOND_CACHE][TILE], cbr[BOND_CACHE][TILE];
     __shared__ uint8_t cbp[BOND_CACHE][TILE];
+    // the tile's atoms in order of decreasing bond count (ties by row): the
+    // loops below run over the atom's bonds and its neighbours' bonds, so the
+    // 64 atoms of a wave then have similar trip counts (each lane's result
+    // depends only on its atom, not on the order)
+    __shared__ uint8_t nb_lds[TILE];
+    __shared__ uint8_t order[TILE];
+    {
+        const int mo = T.row0 + threadIdx.x;
+        const int own = mo < S.n ? S.bcnt[mo] : -1;
+        nb_lds[threadIdx.x] = (uint8_t)(own + 1);
+        __syncthreads();
+        int rank = 0;
+        for (int k = 0; k < TILE; k++) {
+            const int c = (int)nb_lds[k] - 1;
+            rank += (c > own || (c == own && k < (int)threadIdx.x)) ? 1 : 0;
+        }
+        order[rank] = (uint8_t)threadIdx.x;
+    }
     stage_params(Pk, Pl);
     load_dtab2<R>(S, dtab);                 // (ends with a barrier)
     const Params<R> &P = Pl;
-    const int m = T.row0 + threadIdx.x;
+    const int m = T.row0 + order[threadIdx.x];
     if (m >= S.n) return;
     const V4 *xs = reinterpret_cast<const V4 *>(S.xs);
     const V4 *slot = reinterpret_cast<const V4 *>(S.slot);
