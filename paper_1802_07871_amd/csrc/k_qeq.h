@@ -28,9 +28,8 @@ namespace ctbop {
 // Shielded, tapered Coulomb kernel C(r) = ke T(r/rc) (r^3 + g3)^(-1/3) and
 // (dC/dr)/r, evaluated in FP64 for a given distance: an FP32 seed of the
 // reciprocal cube root and one Newton step, y <- y (4 - u y^3) / 3, leave a
-// relative error of ~1e-13, so the only error left in the mixed build is the
-// (unbiased) rounding of r itself.  Summed over ~10^5 charged pairs, a
-// one-sided error of the FP32 functions would otherwise bias the energy.
+// relative error of ~1e-13, so the only error left in the matrix entries is
+// the (unbiased) rounding of r itself and of the stored FP32 value.
 // The radial derivative comes divided by r, without a division: with
 // T'(x) = -140 x^3 (1-x)^3 and x = r/rc,
 //   (dC/dr)/r = ke [ -140 x^2 (1-x)^3 y / rc^2 - T r y^4 ].
@@ -58,6 +57,23 @@ __device__ __forceinline__ double coul64_g(const Params<double> &P, double g3, d
 __device__ __forceinline__ double coul64(const Params<double> &P, int pp, double r, double &dCr)
 {
     return coul64_g(P, P.g3[pp], r, dCr);
+}
+
+// The same in FP32 (the mixed build's force gather): the hardware log2/exp2
+// seed and one FP32 Newton step leave ~1 ulp in y; the pair's energy and
+// force terms are then summed in FP64.  Per pair ~1e-7 relative, against the
+// 1e-6 eV/atom and 1e-5 relative-force budget.
+__device__ __forceinline__ float coul32_g(float ke, float inv_rc, float g3, float r, float &dCr)
+{
+    const float x = r * inv_rc, x2 = x * x, x3 = x2 * x;
+    const float om = 1.0f - x, om2 = om * om;
+    const float T = om2 * om2 * (1.0f + 4.0f * x + 10.0f * x2 + 20.0f * x3);
+    const float u = r * r * r + g3;
+    float y = __builtin_amdgcn_exp2f(-0.333333343f * __builtin_amdgcn_logf(u));
+    y = y * (4.0f - u * y * y * y) * 0.333333343f;
+    const float y2 = y * y;
+    dCr = ke * (-140.0f * inv_rc * inv_rc * x2 * om2 * om * y - T * r * y2 * y2);
+    return ke * T * y;
 }
 
 __device__ __forceinline__ double coul64_val_g(const Params<double> &P, double g3, double r)
@@ -754,6 +770,7 @@ __global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *seg
     const int push = (S.sst->qhead + 1) % NHIST;       // ring slot that takes the previous solution
     constexpr int G = TILE / LPR;
     const int lane = threadIdx.x % LPR;
+    const float ke32 = (float)PD.ke, irc32 = (float)PD.inv_rc;
     double esum = 0.0;
     // bond statistics of the step (for the measurement): bonds and ordered bond pairs
     double nb = 0.0, nt = 0.0;
@@ -767,6 +784,7 @@ __global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *seg
         const V4 li = xs[s];
         const int ti = (int)li.w;
         const double g3_0 = PD.g3[ti * 2], g3_1 = PD.g3[ti * 2 + 1];
+        const float g3f_0 = (float)g3_0, g3f_1 = (float)g3_1;
         const int cnt = S.hcnt[s];
         const auto row = gbl(S.hidx + (size_t)s * S.Wl);
         double ec = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
@@ -781,8 +799,14 @@ __global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *seg
             // distance); a select rather than a branch keeps the loop body in
             // one block, so the charge load issues beside the position load
             const bool in = r < PD.rc;
-            double dCr;
-            double c = coul64_g(PD, (int)lj.w ? g3_1 : g3_0, r, dCr);
+            double dCr, c;
+            if constexpr (sizeof(R) == 4) {
+                float d32;
+                c = (double)coul32_g(ke32, irc32, (int)lj.w ? g3f_1 : g3f_0, (float)r, d32);
+                dCr = (double)d32;
+            } else {
+                c = coul64_g(PD, (int)lj.w ? g3_1 : g3_0, r, dCr);
+            }
             c = in ? c : 0.0;
             dCr = in ? dCr : 0.0;
             ec += c * qj;
