@@ -278,7 +278,7 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
            o_slot = take(v4 * np * S.Wb);
     size_t o_ecov = take(8 * np), o_fcov = take(8 * 3 * np);
     size_t o_q = take(8 * np), o_r = take(8 * np), o_p = take(8 * np), o_s = take(8 * np), o_jd = take(8 * np);
-    size_t o_binv = take(4 * np * BK), o_m1 = take(8 * np), o_y = take(8 * np);
+    size_t o_binv = take(2 * np * BK), o_m1 = take(8 * np), o_y = take(8 * np);
     size_t o_qs = take(8 * (size_t)n), o_qring = take(8 * (size_t)NHIST * n);
     size_t o_part = take(8 * NPART * (size_t)S.ntile);
     const bool fq = ctx->opts.fq_kappa > 0.0;
@@ -331,7 +331,7 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
         S.r = (double *)(base + o_r);
         S.p = (double *)(base + o_p);
         S.s = (double *)(base + o_s);
-        S.binv = (float *)(base + o_binv);
+        S.binv = (_Float16 *)(base + o_binv);
         S.m1 = (double *)(base + o_m1);
         S.y = (double *)(base + o_y);
         S.jd = (double *)(base + o_jd);

@@ -202,7 +202,7 @@ struct Seg {
     // b*BK*BK + t*BK + u), computed in FP32, symmetrised and stored in FP32
     // (so the operator is exactly symmetric); its row sums m1 = M 1 (of the
     // stored entries, FP64) and y = M r
-    float *binv;       // [npad * BK]
+    _Float16 *binv;    // [npad * BK]: row s of its block's inverse at s * BK
     double *m1, *y;    // [npad]
     double *q_state;   // user order charges of the last solve, for the warm start [n]
     double *q_ring;    // the NHIST solves before it, a ring of [NHIST][n] (predictor history; null: none)

@@ -423,13 +423,16 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
         }
         __syncthreads();
     }
+    // row i of the block (symmetrised), rounded to FP16 and stored as the
+    // row's 16 entries; the row sum m1 is taken from the rounded entries, so
+    // that the projection uses exactly the preconditioner that is applied
     double m1 = 0.0;
-    float *bo = S.binv + (size_t)(T.row0 + blk * BK) * BK;
+    _Float16 *bo = S.binv + (size_t)(T.row0 + blk * BK + i) * BK;
 #pragma unroll
     for (int t = 0; t < BK; t++) {
-        const float b = 0.5f * (A[blk][i][t] + A[blk][t][i]);
-        bo[t * BK + i] = b;
-        m1 += (double)b;
+        const _Float16 b = (_Float16)(0.5f * (A[blk][i][t] + A[blk][t][i]));
+        bo[t] = b;
+        m1 += (double)(float)b;
     }
     double v[6] = {0, 0, 0, 0, 0, 0};
     if (live) {
@@ -446,15 +449,23 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
     tile_partials<6>(S, T.row0 / TILE, v, lds);
 }
 
-// y = M r for row s: the row of s's block inverse against the block's r,
-// exchanged by shuffles within the BK lanes of the block (every lane of the
-// block must call it; rows past n pass r = 0).
-__device__ __forceinline__ double block_apply(const float *binv, int s, double r)
+// y = M r for row s: the row of s's block inverse (16 FP16 entries, two
+// 16-byte loads) against the block's r, exchanged by shuffles within the BK
+// lanes of the block (every lane of the block must call it; rows past n pass
+// r = 0).  The inverse only sets the iteration count: symmetric and positive
+// definite after rounding (its entries move by ~5e-4 relative, its smallest
+// eigenvalues are ~1e-2 of its largest), so the solution is unchanged.
+__device__ __forceinline__ double block_apply(const _Float16 *binv, int s, double r)
 {
-    const auto B = gbl(binv + (size_t)(s & ~(BK - 1)) * BK + (s & (BK - 1)));
+    static_assert(BK == 16, "a row of the block is two 16-byte words");
+    typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+    const auto B = gbl(reinterpret_cast<const h8 *>(binv + (size_t)s * BK));
+    const h8 b0 = B[0], b1 = B[1];
     double y = 0.0;
 #pragma unroll
-    for (int t = 0; t < BK; t++) y += (double)B[t * BK] * __shfl(r, t, BK);
+    for (int t = 0; t < 8; t++) y += (double)(float)b0[t] * __shfl(r, t, BK);
+#pragma unroll
+    for (int t = 0; t < 8; t++) y += (double)(float)b1[t] * __shfl(r, 8 + t, BK);
     return y;
 }
 
@@ -491,7 +502,7 @@ __global__ void __launch_bounds__(TILE) k_shift_stats(const Tile *tiles, Seg *se
     const auto rv = gblw(S.r);
     const auto yv = gblw(S.y);
     const auto m1 = gbl(S.m1);
-    const float *binv = S.binv;
+    const _Float16 *binv = S.binv;
     double r = 0.0;
     if (live) {
         const double w = S.sst->w;
@@ -704,7 +715,7 @@ __global__ void __launch_bounds__(TILE) k_cg_update(const Tile *tiles, Seg *segs
     const auto pv = gbl(S.p);
     const auto sv = gbl(S.s);
     const auto m1 = gbl(S.m1);
-    const float *binv = S.binv;
+    const _Float16 *binv = S.binv;
     double q = 0.0, r = 0.0;
     if (live) {
         q = qv[s] + alpha * pv[s];
