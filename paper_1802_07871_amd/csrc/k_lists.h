@@ -461,13 +461,17 @@ __global__ void __launch_bounds__(TILE) k_build(const Tile *tiles, Seg *segs, Pa
                         const int m = mb + lane;
                         bool inl = false, ins = false;
                         uint32_t ent = 0;
-                        const int d2 = m < m1 ? dr + (csort[m] - rowc - er) : 0;
+                        // the candidate's cell and position, both loaded before
+                        // either is used (lanes past the run load its last atom)
+                        const int mc = min(m, m1 - 1);
+                        const int cm = csort[mc];
+                        const V4 lj = ld4<R>(xs, mc);
+                        const int d2 = m < m1 ? dr + (cm - rowc - er) : 0;
                         const int code = code_of(d0, d1, d2);
+                        const V4 D = dtab[code];
+                        R rx = (lj.x - li.x) + D.x, ry = (lj.y - li.y) + D.y, rz = (lj.z - li.z) + D.z;
+                        float r2 = (float)(rx * rx + ry * ry + rz * rz);
                         if (m < m1 && !(m == s && code == CODE_CENTER)) {
-                            const V4 D = dtab[code];
-                            const V4 lj = ld4<R>(xs, m);
-                            R rx = (lj.x - li.x) + D.x, ry = (lj.y - li.y) + D.y, rz = (lj.z - li.z) + D.z;
-                            float r2 = (float)(rx * rx + ry * ry + rz * rz);
                             if (r2 < P.l_cut2) {
                                 inl = true;
                                 if (r2 < P.close2) close = true;
