@@ -175,94 +175,114 @@ __global__ void __launch_bounds__(TILE) k_bond(const Tile *tiles, Seg *segs, Par
     const Seg &S = segs[T.seg];
     __shared__ double4 dtab[NCODE];
     __shared__ Params<double> Pl;
-    // the first BOND_CACHE bonds of each thread's atom: vector, length and
+    // the first BOND_CACHE bonds of each row of the tile: vector, length and
     // pair type, computed once for the triplet loop (the cutoff value is
     // recomputed from the length: 1 below R, which most bonds are, so the
     // block's LDS stays under a third of a CU's and three blocks fit)
     __shared__ double cbx[BOND_CACHE][TILE], cby[BOND_CACHE][TILE], cbz[BOND_CACHE][TILE];
     __shared__ double cbr[BOND_CACHE][TILE];
     __shared__ uint8_t cbp[BOND_CACHE][TILE];
+    __shared__ int nb_lds[TILE];
+    __shared__ uint8_t order[TILE];
     stage_params(Pk, Pl);
     load_dtab2<double>(S, dtab);            // (ends with a barrier)
     const Params<double> &P = Pl;
-    const int s = T.row0 + threadIdx.x;
-    if (s >= S.n) {
-        if (s < S.npad) {
+    const double4 *xs = S.xs64;
+    const int Wb = S.Wb, Ws = S.Ws;
+    // First, one row per lane (the sliced bond arrays are written a whole
+    // segment per wave): the row's bonds, its bond count and the first
+    // bonds' geometry.
+    {
+        const int s = T.row0 + threadIdx.x;
+        int nb = -1;
+        if (s < S.n) {
+            const double4 li = ld4<double>(xs, s);
+            const int ti = (int)li.w;
+            const size_t rl = (size_t)s * Ws;
+            const int ns = S.scnt[s];
+            const auto sidx = gbl(S.sidx + rl);
+            const auto srev = gbl(S.srev + rl);
+            const auto bidx = gblw(S.bidx + slice_base(s, Wb));
+            const auto bsrev = gblw(S.bsrev + slice_base(s, Wb));
+            const auto cmap = gblw(S.cmap + slice_base(s, Ws));
+            nb = 0;
+            for (int e = 0; e < ns; e++) {
+                const uint32_t ent = sidx[e];
+                const double4 lj = ld4<double>(xs, ent & J_MASK);
+                const int pp = ti * 2 + (int)lj.w;
+                const R3<double> d = pair_vec<double>(li, lj, dtab[ent >> CODE_SHIFT]);
+                const double r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+                uint8_t c = 255;
+                if (r2 < P.Sc[pp] * P.Sc[pp]) {
+                    if (nb < Wb) {
+                        bidx[(size_t)nb * SLICE] = ent;
+                        bsrev[(size_t)nb * SLICE] = srev[e];
+                        c = (uint8_t)nb;
+                        if (nb < BOND_CACHE) {
+                            cbx[nb][threadIdx.x] = d.x;
+                            cby[nb][threadIdx.x] = d.y;
+                            cbz[nb][threadIdx.x] = d.z;
+                            cbr[nb][threadIdx.x] = sqrt(r2);
+                            cbp[nb][threadIdx.x] = (uint8_t)pp;
+                        }
+                    }
+                    nb++;
+                }
+                cmap[(size_t)e * SLICE] = c;
+            }
+            if (nb > Wb) {
+                atomicOr(&S.sst->status, ST_OVERFLOW);
+                nb = Wb;
+            }
+            S.bcnt[s] = nb;
+        } else if (s < S.npad) {
             S.ecov[s] = 0.0;
             S.bcnt[s] = 0;
         }
-        return;
+        nb_lds[threadIdx.x] = nb;
     }
-    const double4 *xs = S.xs64;
+    __syncthreads();
+    // Then the triplet sums, bond orders and energies with the tile's rows
+    // in order of decreasing bond count (ties by row): the loops run over
+    // bond pairs, so the 64 rows a wave then holds have similar trip counts
+    // (each row's results depend only on the row, not on the order).
+    {
+        const int own = nb_lds[threadIdx.x];
+        int rank = 0;
+        for (int k = 0; k < TILE; k++) {
+            const int c = nb_lds[k];
+            rank += (c > own || (c == own && k < (int)threadIdx.x)) ? 1 : 0;
+        }
+        order[rank] = (uint8_t)threadIdx.x;
+    }
+    __syncthreads();
+    const int lr = order[threadIdx.x];
+    const int s = T.row0 + lr;
+    if (s >= S.n) return;
+    const int nb = nb_lds[lr];
     const double4 li = ld4<double>(xs, s);
     const int ti = (int)li.w;
-    const int Wb = S.Wb, Ws = S.Ws;
-    const size_t rl = (size_t)s * Ws;
-    const int ns = S.scnt[s];
-    const auto sidx = gbl(S.sidx + rl);
-    const auto srev = gbl(S.srev + rl);
-    const auto bidx = gblw(S.bidx + slice_base(s, Wb));
-    const auto bsrev = gblw(S.bsrev + slice_base(s, Wb));
-    const auto cmap = gblw(S.cmap + slice_base(s, Ws));
-    int nb = 0;
-    for (int e = 0; e < ns; e++) {
-        const uint32_t ent = sidx[e];
-        const double4 lj = ld4<double>(xs, ent & J_MASK);
-        const int pp = ti * 2 + (int)lj.w;
-        const R3<double> d = pair_vec<double>(li, lj, dtab[ent >> CODE_SHIFT]);
-        const double r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-        uint8_t c = 255;
-        if (r2 < P.Sc[pp] * P.Sc[pp]) {
-            if (nb < Wb) {
-                bidx[(size_t)nb * SLICE] = ent;
-                bsrev[(size_t)nb * SLICE] = srev[e];
-                c = (uint8_t)nb;
-            }
-            nb++;
-        }
-        cmap[(size_t)e * SLICE] = c;
-    }
-    if (nb > Wb) {
-        atomicOr(&S.sst->status, ST_OVERFLOW);
-        nb = Wb;
-    }
-    S.bcnt[s] = nb;
     V4 *slot = reinterpret_cast<V4 *>(S.slot) + slice_base(s, Wb);
     const auto row = gbl(S.bidx + slice_base(s, Wb));
-    // bond e of the atom: vector, length, cutoff value, pair type
-    auto bond_geom = [&](int e, R3<double> &d, double &r, double &fcut, int &pp) {
-        const uint32_t ent = row[(size_t)e * SLICE];
-        const double4 lj = ld4<double>(xs, ent & J_MASK);
-        pp = ti * 2 + (int)lj.w;
-        d = pair_vec<double>(li, lj, dtab[ent >> CODE_SHIFT]);
-        r = sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
+    // bond e of the row: vector, length, cutoff value, pair type (the first
+    // BOND_CACHE from LDS)
+    auto bond = [&](int e, R3<double> &d, double &r, double &fcut, int &pp) {
+        if (e < BOND_CACHE) {
+            d.x = cbx[e][lr];
+            d.y = cby[e][lr];
+            d.z = cbz[e][lr];
+            r = cbr[e][lr];
+            pp = cbp[e][lr];
+        } else {
+            const uint32_t ent = row[(size_t)e * SLICE];
+            const double4 lj = ld4<double>(xs, ent & J_MASK);
+            pp = ti * 2 + (int)lj.w;
+            d = pair_vec<double>(li, lj, dtab[ent >> CODE_SHIFT]);
+            r = sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
+        }
         double dummy;
         fcut = cutoff<double>(r, P.Rc[pp], P.Sc[pp], P.piSR[pp], dummy);
     };
-    auto bond = [&](int e, R3<double> &d, double &r, double &fcut, int &pp) {
-        if (e < BOND_CACHE) {
-            d.x = cbx[e][threadIdx.x];
-            d.y = cby[e][threadIdx.x];
-            d.z = cbz[e][threadIdx.x];
-            r = cbr[e][threadIdx.x];
-            pp = cbp[e][threadIdx.x];
-            double dummy;
-            fcut = cutoff<double>(r, P.Rc[pp], P.Sc[pp], P.piSR[pp], dummy);
-        } else {
-            bond_geom(e, d, r, fcut, pp);
-        }
-    };
-    for (int e = 0; e < min(nb, BOND_CACHE); e++) {
-        R3<double> d;
-        double r, fcut;
-        int pp;
-        bond_geom(e, d, r, fcut, pp);
-        cbx[e][threadIdx.x] = d.x;
-        cby[e][threadIdx.x] = d.y;
-        cbz[e][threadIdx.x] = d.z;
-        cbr[e][threadIdx.x] = r;
-        cbp[e][threadIdx.x] = (uint8_t)pp;
-    }
     double ecov = 0.0;
     for (int e = 0; e < nb; e++) {
         R3<double> d;
