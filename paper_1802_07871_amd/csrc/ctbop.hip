@@ -278,9 +278,9 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
            o_slot = take(v4 * np * S.Wb);
     size_t o_ecov = take(8 * np), o_fcov = take(8 * 3 * np);
     size_t o_q = take(8 * np), o_r = take(8 * np), o_p = take(8 * np), o_s = take(8 * np), o_jd = take(8 * np);
-    size_t o_binv = take(2 * np * BK), o_m1 = take(8 * np), o_y = take(8 * np);
+    size_t o_binv = take(2 * np * BK), o_m1 = take(8 * np), o_y = take(8 * np), o_hz = take(8 * np);
     size_t o_qs = take(8 * (size_t)n), o_qring = take(8 * (size_t)NHIST * n);
-    size_t o_part = take(8 * NPART * (size_t)S.ntile);
+    size_t o_part = take(8 * (NPART * (size_t)S.ntile + 16 * FIN_SPLIT));
     const bool fq = ctx->opts.fq_kappa > 0.0;
     size_t o_rl = 0, o_rold = 0, o_wq = 0;
     if (fq) {
@@ -334,6 +334,7 @@ int make_layout(const ctbop_ctx *ctx, int n, const double *box, const int *pbc, 
         S.binv = (_Float16 *)(base + o_binv);
         S.m1 = (double *)(base + o_m1);
         S.y = (double *)(base + o_y);
+        S.hz = (double *)(base + o_hz);
         S.jd = (double *)(base + o_jd);
         S.q_state = (double *)(base + o_qs);
         S.q_ring = (double *)(base + o_qring);
@@ -592,53 +593,59 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
     hipLaunchKernelGGL(k_fin_w0, g1, b, 0, st, sid, P.dseg);
     hipLaunchKernelGGL(k_shift_stats, g, b, 0, st, P.dtiles, P.dseg);
     hipLaunchKernelGGL(k_fin_assemble, g1, b, 0, st, sid, P.dseg, ctl);
+    if (!fq) {
+        // the single-reduction solve's start: the residual's last shift, y = M r
+        Timed t(ctx, 6, st);
+        hipLaunchKernelGGL((k_cg1_update<true>), g, b, 0, st, P.dtiles, P.dseg);
+    }
     HIPCHK(hipGetLastError());
     // charge solve: launch iterations in batches, then read the convergence flag
     int done_it = 0;
     int chunk = ctx->opts.cg_check;
-    if (P.own) chunk = std::max(chunk, std::min(ctx->last_iters[P.base], ctx->opts.cg_maxit));
+    // (the single-reduction solve's first finalize counts no iteration: n
+    // iterations take n + 1 rounds)
+    if (P.own) chunk = std::max(chunk, std::min(ctx->last_iters[P.base], ctx->opts.cg_maxit) + (fq ? 0 : 1));
     int *flag = P.flag_host;
     for (;;) {
         for (int c = 0; c < chunk; c++) {
+            if (!fq) {
+                {
+                    Timed t(ctx, 0, st);
+                    hipLaunchKernelGGL((k_spmv<R, SPMV_U, SP_CG1>), g, b, 0, st, P.dtiles, P.dseg);
+                }
+                hipLaunchKernelGGL(k_cg1_sum, dim3(FIN_SPLIT), b, 0, st, sid, P.dseg);
+                hipLaunchKernelGGL(k_cg1_fin, g1, b, 0, st, sid, P.dseg, ctl);
+                Timed t(ctx, 5, st);
+                hipLaunchKernelGGL((k_cg1_update<false>), g, b, 0, st, P.dtiles, P.dseg);
+                continue;
+            }
             {
                 Timed t(ctx, 6, st);
                 hipLaunchKernelGGL(k_cg_dir, g, b, 0, st, P.dtiles, P.dseg);
             }
-            if (fq) {
-                {
-                    Timed t(ctx, 0, st);
-                    hipLaunchKernelGGL((k_spmv<R, SPMV_U, true>), g, b, 0, st, P.dtiles, P.dseg);
-                }
-                // two Newton steps on the step length
-                for (int pass = 0; pass < 2; pass++) {
-                    hipLaunchKernelGGL(k_fq_ls, g, b, 0, st, P.dtiles, P.dseg, pass);
-                    hipLaunchKernelGGL(k_fq_fin_ls, g1, b, 0, st, sid, P.dseg, pass);
-                }
-                hipLaunchKernelGGL(k_fq_step, g, b, 0, st, P.dtiles, P.dseg);
-                {
-                    Timed t(ctx, 5, st);
-                    hipLaunchKernelGGL(k_fq_resid, g, b, 0, st, P.dtiles, P.dseg);
-                }
-                hipLaunchKernelGGL(k_fq_fin_update, g1, b, 0, st, sid, P.dseg, ctl);
-                continue;
-            }
             {
                 Timed t(ctx, 0, st);
-                hipLaunchKernelGGL((k_spmv<R, SPMV_U>), g, b, 0, st, P.dtiles, P.dseg);
+                hipLaunchKernelGGL((k_spmv<R, SPMV_U, SP_FQ>), g, b, 0, st, P.dtiles, P.dseg);
             }
-            hipLaunchKernelGGL(k_fin_alpha, g1, b, 0, st, sid, P.dseg);
+            // two Newton steps on the step length
+            for (int pass = 0; pass < 2; pass++) {
+                hipLaunchKernelGGL(k_fq_ls, g, b, 0, st, P.dtiles, P.dseg, pass);
+                hipLaunchKernelGGL(k_fq_fin_ls, g1, b, 0, st, sid, P.dseg, pass);
+            }
+            hipLaunchKernelGGL(k_fq_step, g, b, 0, st, P.dtiles, P.dseg);
             {
                 Timed t(ctx, 5, st);
-                hipLaunchKernelGGL(k_cg_update, g, b, 0, st, P.dtiles, P.dseg);
+                hipLaunchKernelGGL(k_fq_resid, g, b, 0, st, P.dtiles, P.dseg);
             }
-            hipLaunchKernelGGL(k_fin_update, g1, b, 0, st, sid, P.dseg, ctl);
+            hipLaunchKernelGGL(k_fq_fin_update, g1, b, 0, st, sid, P.dseg, ctl);
         }
         done_it += chunk;
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(flag, &P.L.seg.sst->done, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (ctx->profile) ev_harvest(ctx);
-        if (flag[0] || done_it >= ctx->opts.cg_maxit + 1) break;
+        // (the single-reduction solve's first finalize counts no iteration)
+        if (flag[0] || done_it >= ctx->opts.cg_maxit + 2) break;
         chunk = ctx->opts.cg_check;
     }
     if (P.own) ctx->last_iters[P.base] = flag[1];

@@ -14,7 +14,7 @@
 namespace ctbop {
 
 constexpr int TILE = 256;
-constexpr int NPART = 8;               // doubles of partial sums per tile
+constexpr int NPART = 16;              // doubles of partial sums per tile
 constexpr int CODE_BITS = 9;           // stencil offset code in the list entry
 constexpr int CODE_SHIFT = 23;         // low 23 bits: neighbour row
 constexpr uint32_t J_MASK = (1u << CODE_SHIFT) - 1u;
@@ -76,6 +76,8 @@ struct SegState {
     int warm;          // per-segment start mode when a launch passes warm < 0 (serving)
     int forces_done;   // serving: forces and energy of the current request are written
     int nrebuild;      // rebuilds since the system buffer was set up
+    int cg_first;      // single-reduction solve: the next finalize is the solve's first
+    int cg_last;       // single-reduction solve: the update now launched is the last
     double w;          // current residual shift
     double rho, alpha, beta, res;
     double sdinv;      // 1^T M 1 (sum of the preconditioner's row sums)
@@ -198,15 +200,15 @@ struct Seg {
     double *Fcov;      // SoA [3 npad]
     double *q, *r, *p, *s, *jd;          // [npad]
     // block-Jacobi preconditioner: the inverse of each diagonal BK x BK block
-    // of H (blocks of BK consecutive sorted rows; entry (t, u) of block b at
-    // b*BK*BK + t*BK + u), computed in FP32, symmetrised and stored in FP32
-    // (so the operator is exactly symmetric); its row sums m1 = M 1 (of the
-    // stored entries, FP64) and y = M r
+    // of H (blocks of BK consecutive sorted rows), computed in FP32,
+    // symmetrised and stored in FP16 (so the operator is exactly symmetric);
+    // its row sums m1 = M 1 (of the stored entries, FP64) and y = M r
     _Float16 *binv;    // [npad * BK]: row s of its block's inverse at s * BK
     double *m1, *y;    // [npad]
+    double *hz;        // [npad]: H y, the single-reduction solve's product
     double *q_state;   // user order charges of the last solve, for the warm start [n]
     double *q_ring;    // the NHIST solves before it, a ring of [NHIST][n] (predictor history; null: none)
-    double *part;      // [NPART * ntile]: partial k of tile t at k * ntile + t
+    double *part;      // [NPART * ntile + 16 * FIN_SPLIT]: partial k of tile t at k * ntile + t, then group sums
     SegState *sst;
     // Charge-dependent coupling of the covalent part (fqk > 0; null arrays
     // otherwise): the bond attraction is scaled by f_q = exp(-fqk (q_i - q_j)^2).
@@ -310,11 +312,33 @@ __device__ __forceinline__ int code_of(int d0, int d1, int d2) { return ((d0 + 3
 __device__ __forceinline__ int code_neg(int c) { return (NCODE - 1) - c; }
 
 // wave64 sum of a double (fixed butterfly order: deterministic)
+// v plus lane-moved copy of v (a DPP move of both 32-bit halves; lanes of
+// rows outside ROWS add 0)
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_add(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+    return v + __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave (every lane active), returned in every
+// lane.  The moves run in the vector ALU (data-parallel-primitive lane
+// moves) instead of LDS permutes: pairs, quads, half rows and rows of 16 by
+// mirrors, then row 0 into row 1 and row 2 into row 3 (broadcast of lane 15
+// of each row), then rows 0-1 into rows 2-3 (lane 31); lane 63 ends with the
+// total.  The order of the additions is fixed.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v = dpp_add<0xb1>(v);          // quad_perm [1, 0, 3, 2]
+    v = dpp_add<0x4e>(v);          // quad_perm [2, 3, 0, 1]
+    v = dpp_add<0x141>(v);         // row_half_mirror
+    v = dpp_add<0x140>(v);         // row_mirror
+    v = dpp_add<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 // sum across a group of `width` consecutive lanes (power of two <= 64)
@@ -437,6 +461,54 @@ __device__ __forceinline__ void seg_total(const Seg &S, double *lds, double (&ou
         for (int k = 0; k < K; k++) v[k] += part[(size_t)k * nt + t];
     }
     block_sum<K>(v, lds, out);
+}
+
+// Two-stage sum of partials 0 .. K-1 over a segment's tiles (the
+// single-reduction solve's finalize, 15 partials per tile): one block alone
+// reads them at ~50 GB/s, the rate of one CU's outstanding misses, so FIN_SPLIT
+// blocks first sum consecutive ranges of tiles (each thread about one tile),
+// and the finalize adds the FIN_SPLIT group sums in order.  The group sums
+// sit after the tiles' partials, 16 doubles per group.
+constexpr int FIN_SPLIT = 16;
+template <int K>
+__device__ __forceinline__ void seg_group_sum(const Seg &S, int grp, double *lds /* 4 * K */)
+{
+    static_assert(K <= 16, "a group keeps 16 sums");
+    const auto part = gbl(S.part);
+    const int nt = S.ntile;
+    const int per = (nt + FIN_SPLIT - 1) / FIN_SPLIT;
+    const int t0 = grp * per, t1 = min(nt, t0 + per);
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) v[k] = 0.0;
+    for (int t = t0 + threadIdx.x; t < t1; t += TILE) {
+#pragma unroll
+        for (int k = 0; k < K; k++) v[k] += part[(size_t)k * nt + t];
+    }
+    double tot[K];
+    block_sum<K>(v, lds, tot);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; k++) S.part[(size_t)NPART * nt + grp * 16 + k] = tot[k];
+    }
+}
+
+// The group sums added in group order (result valid in thread 0).
+template <int K>
+__device__ __forceinline__ void seg_total_groups(const Seg &S, double *lds /* FIN_SPLIT * K */, double (&out)[K])
+{
+    const double *g = S.part + (size_t)NPART * S.ntile;
+    for (int i = threadIdx.x; i < FIN_SPLIT * K; i += blockDim.x) lds[i] = g[(i / K) * 16 + i % K];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            double a = lds[k];
+            for (int b = 1; b < FIN_SPLIT; b++) a += lds[b * K + k];
+            out[k] = a;
+        }
+    }
+    __syncthreads();
 }
 
 } // namespace ctbop

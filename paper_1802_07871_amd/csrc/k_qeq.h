@@ -541,6 +541,8 @@ __global__ void k_fin_assemble(const int *seg_ids, Seg *segs, CgCtl ctl)
         st->mshift = st->mu_prev - w0 - w;
         st->iters = 0;
         st->qshift = 0.0;
+        st->cg_first = 1;
+        st->cg_last = 0;
         st->done = (st->res < ctl.tol) ? 1 : 0;
     }
 }
@@ -627,54 +629,94 @@ __device__ __forceinline__ double spmv_row_halo(const double *hp, const uint16_t
     return a;
 }
 
+// What the product kernel computes besides s = H p: the plain solve's p^T s;
+// with the f_q coupling also p^T r (the line search); in the single-reduction
+// solve the product of y = M r instead, into hz, with the six sums its
+// finalize needs.
+enum SpmvMode { SP_PLAIN = 0, SP_FQ = 1, SP_CG1 = 2 };
+constexpr int P_UPD = 0;    // single-reduction solve: partials 0..8 from the update,
+constexpr int P_PRD = 9;    // 9..14 from the product
+
 // s = H p and the tile's share of p^T s, one slot (row) per lane over the
 // sliced copy; U entries of the row are loaded before their products are
 // summed (U accumulators, combined in a fixed order at the end).  The block
 // first stages p of its tile's halo in LDS; a slice of halo positions then
 // reads 6 bytes per entry from memory and p from LDS.  Slices of 16-bit
 // offsets (the halo did not fit) or full entries gather p from memory.
-// With FQ (the f_q coupling's nonlinear solve) the tile's share of p^T r
-// comes along as a second partial, for the line search.
-template <typename R, int U, bool FQ = false>
+template <typename R, int U, int MODE = SP_PLAIN>
 __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
 {
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
-    if (S.sst->done) return;
-    __shared__ double lds[4 * 2];
+    if (S.sst->done || (MODE == SP_CG1 && S.sst->cg_last)) return;
+    __shared__ double lds[4 * 6];
     __shared__ double hp[HALO_MAX];
+    const double *x = MODE == SP_CG1 ? S.y : S.p;
+    // rows in order (the epilogue's loads and stores coalesce), loaded
+    // first so that their latency hides behind the staging and the rows
+    const int row = T.row0 + threadIdx.x;
+    const bool live = row < S.n;
+    double xs = 0.0, jd = 0.0, m1s = 0.0, rs = 0.0, ss = 0.0;
+    if (live) {
+        xs = x[row];
+        jd = S.jd[row];
+        if (MODE == SP_CG1) {
+            m1s = S.m1[row];
+            rs = S.r[row];
+            ss = S.s[row];
+        }
+        if (MODE == SP_FQ) rs = S.r[row];
+    }
     const int tl = T.row0 / TILE;
     const int nh = S.nhalo[tl];
     if (nh <= HALO_MAX) {
         const auto hl = gbl(S.halo + (size_t)tl * HALO_MAX);
-        const auto pg = gbl(S.p);
+        const auto pg = gbl(x);
         for (int k = threadIdx.x; k < nh; k += TILE) hp[k] = pg[hl[k]];
     }
     __syncthreads();
+    // lane = slot: its row's off-diagonal sum, handed to the row's lane in LDS
     const int slot = T.row0 + threadIdx.x;
-    const int s = T.row0 + S.hperm[slot];
-    double pap = 0.0, pr = 0.0;
+    const int rl = S.hperm[slot];
+    const int s = T.row0 + rl;
+    double a = 0.0;
     if (s < S.n) {
         const size_t b0 = slice_base(slot, S.Wl);
         const R *hrow = reinterpret_cast<const R *>(S.H) + b0;
         const int cnt = S.hcnt[s];
         const int mode = S.swide[slot / SLICE];
-        const double a = mode == SL_HALO   ? spmv_row_halo<R, U>(hp, S.hs16 + b0, hrow, cnt)
-                         : mode == SL_FULL ? spmv_row<R, U, uint32_t>(S.p, S.hsidx + b0, hrow, cnt, 0)
-                                           : spmv_row<R, U, uint16_t>(S.p, S.hs16 + b0, hrow, cnt,
-                                                                      (slot & ~(SLICE - 1)) - 32768);
-        const double ps = S.p[s];
-        const double y = S.jd[s] * ps + a;
-        S.s[s] = y;
-        pap = ps * y;
-        if (FQ) pr = ps * S.r[s];
+        a = mode == SL_HALO   ? spmv_row_halo<R, U>(hp, S.hs16 + b0, hrow, cnt)
+            : mode == SL_FULL ? spmv_row<R, U, uint32_t>(x, S.hsidx + b0, hrow, cnt, 0)
+                              : spmv_row<R, U, uint16_t>(x, S.hs16 + b0, hrow, cnt, (slot & ~(SLICE - 1)) - 32768);
     }
-    if (FQ) {
-        double v[2] = {pap, pr};
-        tile_partials<2>(S, T.row0 / TILE, v, lds);
+    __syncthreads();
+    hp[rl] = a;
+    __syncthreads();
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (live) {
+        const double y = jd * xs + hp[threadIdx.x];
+        if (MODE == SP_CG1) {
+            S.hz[row] = y;
+            v[0] = xs * y;                   // y^T H y
+            v[1] = m1s * y;                  // m1^T H y
+            v[2] = rs * y;                   // r^T H y
+            v[3] = y * y;
+            v[4] = ss * y;                   // s_old^T H y
+            v[5] = y;
+        } else {
+            S.s[row] = y;
+            v[0] = xs * y;
+            if (MODE == SP_FQ) v[1] = xs * rs;
+        }
+    }
+    if (MODE == SP_CG1) {
+        tile_partials_at<6>(S, tl, v, lds, P_PRD);
+    } else if (MODE == SP_FQ) {
+        double w[2] = {v[0], v[1]};
+        tile_partials<2>(S, tl, w, lds);
     } else {
-        double v[1] = {pap};
-        tile_partials<1>(S, T.row0 / TILE, v, lds);
+        double w[1] = {v[0]};
+        tile_partials<1>(S, tl, w, lds);
     }
 }
 
@@ -759,6 +801,149 @@ __global__ void k_fin_update(const int *seg_ids, Seg *segs, CgCtl ctl)
         st->qshift = (S.Q - tot[4]) / S.n;
         if (st->res < ctl.tol) st->done = 1;
         else if (st->iters >= ctl.maxit) { st->done = 1; atomicOr(&st->status, ST_NOCONV); }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The same projected PCG with one reduction per iteration (Chronopoulos and
+// Gear's rearrangement of conjugate gradients): the product is taken of
+// y = M r, the unprojected preconditioned residual, and the direction's
+// product follows by recurrence, s = H y + beta s.  The projection enters as
+// the shift c of the residual, r <- r - c 1 with c = m1^T r / 1^T M 1, so that
+// y = M r is the projected preconditioned residual; c of the next residual is
+// known one step ahead from m1^T r and m1^T s.  The finalize also takes the
+// projected norm of the next residual, |r|^2 - 2 alpha r^T s + alpha^2 |s|^2
+// (each minus its mean part), from sums of the two kernels, so the solve
+// stops after the update that meets the tolerance without a further product.
+// An iteration is three launches: product (k_spmv, SP_CG1), finalize, update.
+// ---------------------------------------------------------------------------
+
+// p <- y + beta p, s <- H y + beta s, q <- q + alpha p, r <- r - alpha s - c,
+// y <- M r, and the tile's sums for the finalize.  FIRST: the solve's start,
+// which only shifts r (by the shift left after the second pass) and clears
+// p and s.
+template <bool FIRST>
+__global__ void __launch_bounds__(TILE) k_cg1_update(const Tile *tiles, Seg *segs)
+{
+    const Tile T = my_tile(tiles);
+    const Seg &S = segs[T.seg];
+    if (S.sst->done) return;
+    __shared__ double lds[4 * 9];
+    const int s = T.row0 + threadIdx.x;
+    const bool live = s < S.n;
+    const double alpha = S.sst->alpha, beta = S.sst->beta, c = S.sst->w;
+    // the segment's pointers in registers before the first store
+    const auto qv = gblw(S.q);
+    const auto rv = gblw(S.r);
+    const auto yv = gblw(S.y);
+    const auto pv = gblw(S.p);
+    const auto sv = gblw(S.s);
+    const auto hz = gbl(S.hz);
+    const auto m1 = gbl(S.m1);
+    const _Float16 *binv = S.binv;
+    double q = 0.0, r = 0.0, sn = 0.0;
+    if (live) {
+        if (FIRST) {
+            q = qv[s];
+            r = rv[s] - c;
+            pv[s] = 0.0;
+            sv[s] = 0.0;
+        } else {
+            const double p = yv[s] + beta * pv[s];
+            sn = hz[s] + beta * sv[s];
+            q = qv[s] + alpha * p;
+            r = (rv[s] - alpha * sn) - c;
+            pv[s] = p;
+            sv[s] = sn;
+            qv[s] = q;
+        }
+        rv[s] = r;
+    }
+    const double y = block_apply(binv, s, r);
+    double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (live) {
+        yv[s] = y;
+        const double m = m1[s];
+        v[0] = r * m;
+        v[1] = r * y;
+        v[2] = r;
+        v[3] = r * r;
+        v[4] = q;
+        v[5] = sn * m;
+        v[6] = r * sn;
+        v[7] = sn * sn;
+        v[8] = sn;
+    }
+    tile_partials_at<9>(S, T.row0 / TILE, v, lds, P_UPD);
+}
+
+// The residual after the last update and the stop test; then gamma = r^T y,
+// delta = y^T H y, beta = gamma / gamma_old, alpha = gamma / (delta -
+// beta gamma / alpha_old) (= gamma / p^T H p), the next shift c and the
+// projected norm of the next residual, which marks the coming update as the
+// last when it meets the tolerance.
+// First stage of the finalize: FIN_SPLIT blocks per segment, each summing
+// the 15 partials over its range of tiles.
+__global__ void __launch_bounds__(TILE) k_cg1_sum(const int *seg_ids, Seg *segs)
+{
+    const Seg &S = segs[seg_ids[blockIdx.x / FIN_SPLIT]];
+    if (S.sst->done) return;
+    __shared__ double lds[4 * 15];
+    seg_group_sum<15>(S, blockIdx.x % FIN_SPLIT, lds);
+}
+
+__global__ void __launch_bounds__(TILE) k_cg1_fin(const int *seg_ids, Seg *segs, CgCtl ctl)
+{
+    const Seg &S = segs[seg_ids[blockIdx.x]];
+    if (S.sst->done) return;
+    __shared__ double lds[FIN_SPLIT * 15];
+    double t[15];
+    seg_total_groups<15>(S, lds, t);
+    if (threadIdx.x == 0) {
+        SegState *st = S.sst;
+        const double n = S.n;
+        const double rr = t[P_UPD + 3] - t[P_UPD + 2] * t[P_UPD + 2] / n;
+        st->res = sqrt(fmax(rr / n, 0.0));
+        st->qshift = (S.Q - t[P_UPD + 4]) / n;
+        const bool first = st->cg_first != 0;
+        if (!first) {
+            st->iters += 1;
+            st->iters_total += 1;
+        }
+        if (st->cg_last || st->res < ctl.tol) {
+            st->done = 1;
+            return;
+        }
+        if (st->iters >= ctl.maxit) {
+            st->done = 1;
+            atomicOr(&st->status, ST_NOCONV);
+            return;
+        }
+        const double gam = t[P_UPD + 1], del = t[P_PRD + 0];
+        const double beta = first ? 0.0 : gam / st->rho;
+        const double den = first ? del : del - beta * gam / st->alpha;
+        if (!(den > 0.0) || !(gam > 0.0)) {
+            atomicOr(&st->status, ST_NOT_PD);
+            st->done = 1;
+            return;
+        }
+        const double alpha = gam / den;
+        // sums of the new s = H y + beta s_old
+        const double m1s = t[P_PRD + 1] + beta * t[P_UPD + 5];
+        const double rs = t[P_PRD + 2] + beta * t[P_UPD + 6];
+        const double ss = t[P_PRD + 3] + 2.0 * beta * t[P_PRD + 4] + beta * beta * t[P_UPD + 7];
+        const double sum_s = t[P_PRD + 5] + beta * t[P_UPD + 8];
+        const double c = (t[P_UPD + 0] - alpha * m1s) / st->sdinv;
+        const double rs_p = rs - t[P_UPD + 2] * sum_s / n;
+        const double ss_p = ss - sum_s * sum_s / n;
+        const double next2 = (rr - 2.0 * alpha * rs_p + alpha * alpha * ss_p) / n;
+        st->cg_first = 0;
+        st->rho = gam;
+        st->alpha = alpha;
+        st->beta = beta;
+        st->w = c;
+        st->mshift -= c;
+        if (next2 < ctl.tol * ctl.tol) st->cg_last = 1;
     }
 }
 

@@ -329,22 +329,24 @@ int server_tick(ctbop_server *S, const Params<R> &prm, int cg_iters, bool poll)
         hipLaunchKernelGGL(k_fin_w0, gs, b, 0, st, sid, S->dsegs);
         hipLaunchKernelGGL(k_shift_stats, g, b, 0, st, T, S->dsegs);
         hipLaunchKernelGGL(k_fin_assemble, gs, b, 0, st, sid, S->dsegs, ctl);
+        hipLaunchKernelGGL((k_cg1_update<true>), g, b, 0, st, T, S->dsegs);
     }
     {
         const dim3 g(nta), gs(nia);
         const int *sid = S->dids_act;
         Tile *T = S->dtiles_act;
         CgCtl ctl{ctx->opts.cg_tol, ctx->opts.cg_maxit};
-        const int limit = poll ? ctx->opts.cg_maxit + 1 : cg_iters;
+        // single-reduction solve: a solve of n iterations takes n + 1 rounds
+        // (its first finalize counts none)
+        const int limit = poll ? ctx->opts.cg_maxit + 2 : cg_iters;
         for (int c = 0; c < limit;) {
-            const int first = std::max(ctx->opts.cg_check, std::min(S->iters_hint, ctx->opts.cg_maxit));
+            const int first = std::max(ctx->opts.cg_check, std::min(S->iters_hint, ctx->opts.cg_maxit) + 1);
             const int chunk = poll ? std::min(limit - c, c == 0 ? first : ctx->opts.cg_check) : cg_iters;
             for (int k = 0; k < chunk; k++) {
-                hipLaunchKernelGGL(k_cg_dir, g, b, 0, st, T, S->dsegs);
-                hipLaunchKernelGGL((k_spmv<R, SPMV_U>), g, b, 0, st, T, S->dsegs);
-                hipLaunchKernelGGL(k_fin_alpha, gs, b, 0, st, sid, S->dsegs);
-                hipLaunchKernelGGL(k_cg_update, g, b, 0, st, T, S->dsegs);
-                hipLaunchKernelGGL(k_fin_update, gs, b, 0, st, sid, S->dsegs, ctl);
+                hipLaunchKernelGGL((k_spmv<R, SPMV_U, SP_CG1>), g, b, 0, st, T, S->dsegs);
+                hipLaunchKernelGGL(k_cg1_sum, dim3(nia * FIN_SPLIT), b, 0, st, sid, S->dsegs);
+                hipLaunchKernelGGL(k_cg1_fin, gs, b, 0, st, sid, S->dsegs, ctl);
+                hipLaunchKernelGGL((k_cg1_update<false>), g, b, 0, st, T, S->dsegs);
             }
             c += chunk;
             if (!poll || c >= limit) break;
