@@ -96,6 +96,7 @@ struct SegState {
     // charge coupling (f_q) solve: p^T r, p^T H p and the coupling part of
     // phi'(0) along the current direction (line search)
     double pr, ps, A0;
+    double m1s;        // single-reduction solve: m1^T s of the current direction
 };
 
 // ---------------------------------------------------------------------------

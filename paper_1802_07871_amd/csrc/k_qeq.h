@@ -634,8 +634,9 @@ __device__ __forceinline__ double spmv_row_halo(const double *hp, const uint16_t
 // solve the product of y = M r instead, into hz, with the six sums its
 // finalize needs.
 enum SpmvMode { SP_PLAIN = 0, SP_FQ = 1, SP_CG1 = 2 };
-constexpr int P_UPD = 0;    // single-reduction solve: partials 0..8 from the update,
-constexpr int P_PRD = 9;    // 9..14 from the product
+constexpr int P_UPD = 0;    // single-reduction solve: partials 0..7 from the update,
+constexpr int P_PRD = 8;    // 8..13 from the product
+constexpr int P_CG1 = 14;   // partials the finalize adds up
 
 // s = H p and the tile's share of p^T s, one slot (row) per lane over the
 // sliced copy; U entries of the row are loaded before their products are
@@ -654,6 +655,8 @@ __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
     const double *x = MODE == SP_CG1 ? S.y : S.p;
     // rows in order (the epilogue's loads and stores coalesce), loaded
     // first so that their latency hides behind the staging and the rows
+    // (also in the FP64 kernel, where they cost a wave per SIMD: loading
+    // them after the rows was slower)
     const int row = T.row0 + threadIdx.x;
     const bool live = row < S.n;
     double xs = 0.0, jd = 0.0, m1s = 0.0, rs = 0.0, ss = 0.0;
@@ -828,7 +831,7 @@ __global__ void __launch_bounds__(TILE) k_cg1_update(const Tile *tiles, Seg *seg
     const Tile T = my_tile(tiles);
     const Seg &S = segs[T.seg];
     if (S.sst->done) return;
-    __shared__ double lds[4 * 9];
+    __shared__ double lds[4 * 8];
     const int s = T.row0 + threadIdx.x;
     const bool live = s < S.n;
     const double alpha = S.sst->alpha, beta = S.sst->beta, c = S.sst->w;
@@ -839,7 +842,6 @@ __global__ void __launch_bounds__(TILE) k_cg1_update(const Tile *tiles, Seg *seg
     const auto pv = gblw(S.p);
     const auto sv = gblw(S.s);
     const auto hz = gbl(S.hz);
-    const auto m1 = gbl(S.m1);
     const _Float16 *binv = S.binv;
     double q = 0.0, r = 0.0, sn = 0.0;
     if (live) {
@@ -860,21 +862,19 @@ __global__ void __launch_bounds__(TILE) k_cg1_update(const Tile *tiles, Seg *seg
         rv[s] = r;
     }
     const double y = block_apply(binv, s, r);
-    double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (live) {
         yv[s] = y;
-        const double m = m1[s];
-        v[0] = r * m;
+        v[0] = y;                // 1^T M r = m1^T r (M symmetric)
         v[1] = r * y;
         v[2] = r;
         v[3] = r * r;
         v[4] = q;
-        v[5] = sn * m;
-        v[6] = r * sn;
-        v[7] = sn * sn;
-        v[8] = sn;
+        v[5] = r * sn;
+        v[6] = sn * sn;
+        v[7] = sn;
     }
-    tile_partials_at<9>(S, T.row0 / TILE, v, lds, P_UPD);
+    tile_partials_at<8>(S, T.row0 / TILE, v, lds, P_UPD);
 }
 
 // The residual after the last update and the stop test; then gamma = r^T y,
@@ -888,17 +888,17 @@ __global__ void __launch_bounds__(TILE) k_cg1_sum(const int *seg_ids, Seg *segs)
 {
     const Seg &S = segs[seg_ids[blockIdx.x / FIN_SPLIT]];
     if (S.sst->done) return;
-    __shared__ double lds[4 * 15];
-    seg_group_sum<15>(S, blockIdx.x % FIN_SPLIT, lds);
+    __shared__ double lds[4 * P_CG1];
+    seg_group_sum<P_CG1>(S, blockIdx.x % FIN_SPLIT, lds);
 }
 
 __global__ void __launch_bounds__(TILE) k_cg1_fin(const int *seg_ids, Seg *segs, CgCtl ctl)
 {
     const Seg &S = segs[seg_ids[blockIdx.x]];
     if (S.sst->done) return;
-    __shared__ double lds[FIN_SPLIT * 15];
-    double t[15];
-    seg_total_groups<15>(S, lds, t);
+    __shared__ double lds[FIN_SPLIT * P_CG1];
+    double t[P_CG1];
+    seg_total_groups<P_CG1>(S, lds, t);
     if (threadIdx.x == 0) {
         SegState *st = S.sst;
         const double n = S.n;
@@ -928,16 +928,19 @@ __global__ void __launch_bounds__(TILE) k_cg1_fin(const int *seg_ids, Seg *segs,
             return;
         }
         const double alpha = gam / den;
-        // sums of the new s = H y + beta s_old
-        const double m1s = t[P_PRD + 1] + beta * t[P_UPD + 5];
-        const double rs = t[P_PRD + 2] + beta * t[P_UPD + 6];
-        const double ss = t[P_PRD + 3] + 2.0 * beta * t[P_PRD + 4] + beta * beta * t[P_UPD + 7];
-        const double sum_s = t[P_PRD + 5] + beta * t[P_UPD + 8];
+        // sums of the new s = H y + beta s_old (m1^T s by its own recurrence:
+        // an error in it only leaves m1^T r of the next residual slightly off
+        // zero, and the next shift, from the measured m1^T r, removes that)
+        const double m1s = first ? t[P_PRD + 1] : t[P_PRD + 1] + beta * st->m1s;
+        const double rs = t[P_PRD + 2] + beta * t[P_UPD + 5];
+        const double ss = t[P_PRD + 3] + 2.0 * beta * t[P_PRD + 4] + beta * beta * t[P_UPD + 6];
+        const double sum_s = t[P_PRD + 5] + beta * t[P_UPD + 7];
         const double c = (t[P_UPD + 0] - alpha * m1s) / st->sdinv;
         const double rs_p = rs - t[P_UPD + 2] * sum_s / n;
         const double ss_p = ss - sum_s * sum_s / n;
         const double next2 = (rr - 2.0 * alpha * rs_p + alpha * alpha * ss_p) / n;
         st->cg_first = 0;
+        st->m1s = m1s;
         st->rho = gam;
         st->alpha = alpha;
         st->beta = beta;
