@@ -583,9 +583,10 @@ def main():
     ms, cnt = prof["spmv"]
     iters = int(info["cg_iters_total"]) - int(info_w["cg_iters_total"])
     avg_s = ms / 1e3 / max(iters, 1)
-    # entry: FP32 value + 16-bit row offset (32-bit index in wide slices);
-    # row: count, p_i, J_i, result s_i
-    spmv_bytes = 6.0 * nnz + 2.0 * nnz_wide + 28.0 * n
+    # entry: FP32 value + 16-bit halo position or offset (32-bit index in wide
+    # slices); row: count, y_i, J_i, the result (H y)_i, and m1_i, r_i, s_i for
+    # the single-reduction solve's sums
+    spmv_bytes = 6.0 * nnz + 2.0 * nnz_wide + 52.0 * n
     achieved = spmv_bytes / avg_s / 1e9
     fms, fcnt = prof["force_coul"]
     f_avg = fms / 1e3 / max(fcnt, 1)
@@ -618,7 +619,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(),
                      "measured_copy_peak_GBps": copy_peak,
-                     "kernel": "k_spmv (charge-solve H p)", "bytes_per_launch": spmv_bytes, "launches": iters,
+                     "kernel": "k_spmv (charge-solve H y, single-reduction PCG)", "bytes_per_launch": spmv_bytes, "launches": iters,
                      "avg_launch_us": avg_s * 1e6},
         "roofline_force": {"bound": "hbm", "achieved": force_bytes / f_avg / 1e9 if fcnt else None,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
