@@ -231,9 +231,9 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
 // the tile one slice (SLICE slots) at a time through LDS, in chunks of HS_CH
 // entries per row: four lanes read one row's chunk as whole 128-byte lines
 // of hidx and Hr, and add the entries whose neighbour lies in the row's own
-// BK-row block to their part of that block row; then every lane writes
-// entries of its slot as slice columns (64 lanes store contiguous memory).
-// The four parts of each block row are added in a fixed order.  The tile's
+// BK-row block into that block row in LDS, the four lanes in turn (so the
+// additions keep list order); then every lane writes entries of its slot as
+// slice columns (64 lanes store contiguous memory).  The tile's
 // blocks (J on the diagonal) are then inverted in LDS by Gauss-Jordan
 // elimination in FP32 (H is SPD and its blocks well conditioned, so no
 // pivoting; the preconditioner only has to be symmetric positive definite,
@@ -282,6 +282,8 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
     const bool live = own < S.n;
     const int own_cnt = live ? S.hcnt[own] : 0;
     cnt_lds[tid] = own_cnt;
+    float *Af = &A[0][0][0];
+    for (int w = tid; w < TILE / BK * BK * (BK + 1); w += TILE) Af[w] = 0.0f;
     wide_row[tid] = (live && S.hwide[own] != 0) ? 1 : 0;
     // the tile's halo bitmap: an entry's place in the halo is the set bits before its own
     const int tl = T.row0 / TILE;
@@ -337,9 +339,7 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
         const int wl = tid % SLICE, wq = tid / SLICE;
         const int wcnt = slot_cnt[slot0 + wl];
         const size_t b0 = slice_base(sbase + wl, S.Wl);
-        float hb[BK];
-#pragma unroll
-        for (int t = 0; t < BK; t++) hb[t] = 0.0f;
+        float *arow = &A[rrk / BK][rrk % BK][0];
         for (int E0 = 0; E0 < mlen; E0 += HS_CH) {
             const int e0 = E0 + rq * 8;
             if (e0 < rcnt) {
@@ -351,11 +351,20 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
                 for (int k = 0; k < 8; k++) {
                     ci[rl][rq * 8 + k] = ie[k];
                     cv[rl][rq * 8 + k] = ve[k];
-                    const unsigned col = (unsigned)((int)(ie[k] & J_MASK) - rbb);
-                    if (e0 + k < rcnt && col < (unsigned)BK) {
+                }
+                // entries whose neighbour lies in the row's own block, added
+                // into its block row by the row's four lanes in turn (the
+                // lanes of one wave: their LDS accesses stay in order), so
+                // the additions keep list order
+                for (int q4 = 0; q4 < HS_LPR; q4++) {
+                    if (rq == q4) {
 #pragma unroll
-                        for (int t = 0; t < BK; t++) hb[t] += (col == (unsigned)t) ? (float)ve[k] : 0.0f;
+                        for (int k = 0; k < 8; k++) {
+                            const unsigned col = (unsigned)((int)(ie[k] & J_MASK) - rbb);
+                            if (e0 + k < rcnt && col < (unsigned)BK) arow[col] += (float)ve[k];
+                        }
                     }
+                    __builtin_amdgcn_wave_barrier();
                 }
             }
             __syncthreads();
@@ -378,16 +387,6 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
                 }
             }
             __syncthreads();
-        }
-        // the slot's block row: the four readers' parts, added pairwise
-#pragma unroll
-        for (int t = 0; t < BK; t++) {
-            hb[t] += __shfl_xor(hb[t], 1, 64);
-            hb[t] += __shfl_xor(hb[t], 2, 64);
-        }
-        if (rq == 0) {
-#pragma unroll
-            for (int t = 0; t < BK; t++) A[rrk / BK][rrk % BK][t] = hb[t];
         }
     }
     __syncthreads();
