@@ -550,32 +550,41 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
     hipStream_t st = P.st;
     const int *sid = P.dsegid;
     launch_lists<R>(ctx, P, prm, flags);
-    // covalent terms on the side stream: they need only the lists and
-    // overlap the assembly, the charge solve and its host round trips (a
-    // fork after the sliced copy, overlapping the solve only, was slower)
-    hipStream_t cst = st;
-    if (P.own) {
-        int rc = side_stream(ctx);
-        if (rc) return rc;
-        HIPCHK(hipEventRecord(ctx->ev_fork, st));
-        HIPCHK(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
-        cst = ctx->side;
-    }
-    // with the charge coupling the covalent gather needs the charges: the
-    // side stream then runs the bond pass and the coupling weights only, and
-    // the gather follows the solve on the caller's stream
+    // covalent terms on the side stream: they need only the lists, and run
+    // beside the charge solve and its host round trips, forked after the
+    // sliced copy (beside the assembly and the copy they slowed both by more
+    // than the solve loses).  With the charge coupling the covalent gather
+    // needs the charges: the side stream then runs the bond pass and the
+    // coupling weights only, forked before the assembly since the starting
+    // residual needs those weights, and the gather follows the solve on the
+    // caller's stream.
     const bool fq = ctx->opts.fq_kappa > 0.0;
-    {
-        Timed t(ctx, 3, cst);
-        hipLaunchKernelGGL((k_bond<R>), g, b, 0, cst, P.dtiles, P.dseg, ctx->pd);
-    }
+    auto side_launch = [&]() -> int {
+        hipStream_t cst = st;
+        if (P.own) {
+            int rc = side_stream(ctx);
+            if (rc) return rc;
+            HIPCHK(hipEventRecord(ctx->ev_fork, st));
+            HIPCHK(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+            cst = ctx->side;
+        }
+        {
+            Timed t(ctx, 3, cst);
+            hipLaunchKernelGGL((k_bond<R>), g, b, 0, cst, P.dtiles, P.dseg, ctx->pd);
+        }
+        if (fq) {
+            hipLaunchKernelGGL((k_fq_weight<R>), g, b, 0, cst, P.dtiles, P.dseg);
+        } else {
+            Timed t(ctx, 4, cst);
+            hipLaunchKernelGGL((k_force_cov<R>), g, b, 0, cst, P.dtiles, P.dseg, prm, 0);
+        }
+        if (P.own) HIPCHK(hipEventRecord(ctx->ev_join, ctx->side));
+        return CTBOP_OK;
+    };
     if (fq) {
-        hipLaunchKernelGGL((k_fq_weight<R>), g, b, 0, cst, P.dtiles, P.dseg);
-    } else {
-        Timed t(ctx, 4, cst);
-        hipLaunchKernelGGL((k_force_cov<R>), g, b, 0, cst, P.dtiles, P.dseg, prm, 0);
+        const int rc = side_launch();
+        if (rc) return rc;
     }
-    if (P.own) HIPCHK(hipEventRecord(ctx->ev_join, ctx->side));
     CgCtl ctl{ctx->opts.cg_tol, ctx->opts.cg_maxit};
     {
         Timed t(ctx, 2, st);
@@ -589,6 +598,10 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
     {
         Timed t(ctx, 8, st);
         hipLaunchKernelGGL((k_hslice<R>), g, b, 0, st, P.dtiles, P.dseg);
+    }
+    if (!fq) {
+        const int rc = side_launch();
+        if (rc) return rc;
     }
     hipLaunchKernelGGL(k_fin_w0, g1, b, 0, st, sid, P.dseg);
     hipLaunchKernelGGL(k_shift_stats, g, b, 0, st, P.dtiles, P.dseg);
