@@ -158,20 +158,22 @@ int launch_param_grad(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, char *adj, 
     HIPCHK(hipMemcpyAsync(&res0, &asst->res0, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     ctl.tol = std::max(ctx->opts.cg_tol * res0, 1e-300);
+    // the single-reduction solve of the forward one (its first finalize
+    // counts no iteration)
+    hipLaunchKernelGGL((k_cg1_update<true>), g, b, 0, st, P.dtiles, dadj);
     int done_it = 0;
     for (;;) {
         for (int c = 0; c < ctx->opts.cg_check; c++) {
-            hipLaunchKernelGGL(k_cg_dir, g, b, 0, st, P.dtiles, dadj);
-            hipLaunchKernelGGL((k_spmv<R, SPMV_U>), g, b, 0, st, P.dtiles, dadj);
-            hipLaunchKernelGGL(k_fin_alpha, g1, b, 0, st, sid, dadj);
-            hipLaunchKernelGGL(k_cg_update, g, b, 0, st, P.dtiles, dadj);
-            hipLaunchKernelGGL(k_fin_update, g1, b, 0, st, sid, dadj, ctl);
+            hipLaunchKernelGGL((k_spmv<R, SPMV_U, SP_CG1>), g, b, 0, st, P.dtiles, dadj);
+            hipLaunchKernelGGL(k_cg1_sum, dim3(FIN_SPLIT), b, 0, st, sid, dadj);
+            hipLaunchKernelGGL(k_cg1_fin, g1, b, 0, st, sid, dadj, ctl);
+            hipLaunchKernelGGL((k_cg1_update<false>), g, b, 0, st, P.dtiles, dadj);
         }
         done_it += ctx->opts.cg_check;
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(ctx->host_flag, &asst->done, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (ctx->host_flag[0] || done_it >= ctx->opts.cg_maxit + 1) break;
+        if (ctx->host_flag[0] || done_it >= ctx->opts.cg_maxit + 2) break;
     }
     if (cg_iters) *cg_iters = ctx->host_flag[1];
     hipLaunchKernelGGL(k_adj_keep_lam_shift, g1, dim3(64), 0, st, sid, dadj, A);
