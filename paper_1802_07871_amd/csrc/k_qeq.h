@@ -546,7 +546,8 @@ __global__ void k_fin_assemble(const int *seg_ids, Seg *segs, CgCtl ctl)
     }
 }
 
-// r <- r - w,  p <- M (r - w 1) + beta p = (y - w m1) + beta p
+// r <- r - w,  p <- M (r - w 1) + beta p = (y - w m1) + beta p (the charge
+// coupling's nonlinear solve; the linear solves use the single-reduction form)
 __global__ void __launch_bounds__(TILE) k_cg_dir(const Tile *tiles, Seg *segs)
 {
     const Tile T = my_tile(tiles);
@@ -719,90 +720,6 @@ __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
     } else {
         double w[1] = {v[0]};
         tile_partials<1>(S, tl, w, lds);
-    }
-}
-
-// alpha = rho / p^T H p
-__global__ void k_fin_alpha(const int *seg_ids, Seg *segs)
-{
-    const Seg &S = segs[seg_ids[blockIdx.x]];
-    if (S.sst->done) return;
-    __shared__ double lds[4];
-    double tot[1];
-    seg_total<1>(S, lds, tot);
-    if (threadIdx.x == 0) {
-        SegState *st = S.sst;
-        if (!(tot[0] > 0.0)) {
-            atomicOr(&st->status, ST_NOT_PD);
-            st->done = 1;
-            st->alpha = 0.0;
-        } else {
-            st->alpha = st->rho / tot[0];
-        }
-    }
-}
-
-// q += alpha p, r -= alpha s, y = M r, and the tile's sums for w, rho and the test
-__global__ void __launch_bounds__(TILE) k_cg_update(const Tile *tiles, Seg *segs)
-{
-    const Tile T = my_tile(tiles);
-    const Seg &S = segs[T.seg];
-    if (S.sst->done) return;
-    __shared__ double lds[4 * 5];
-    const int s = T.row0 + threadIdx.x;
-    const bool live = s < S.n;
-    const double alpha = S.sst->alpha;
-    // the segment's pointers in registers before the first store
-    const auto qv = gblw(S.q);
-    const auto rv = gblw(S.r);
-    const auto yv = gblw(S.y);
-    const auto pv = gbl(S.p);
-    const auto sv = gbl(S.s);
-    const auto m1 = gbl(S.m1);
-    const _Float16 *binv = S.binv;
-    double q = 0.0, r = 0.0;
-    if (live) {
-        q = qv[s] + alpha * pv[s];
-        r = rv[s] - alpha * sv[s];
-        qv[s] = q;
-        rv[s] = r;
-    }
-    const double y = block_apply(binv, s, r);
-    double v[5] = {0, 0, 0, 0, 0};
-    if (live) {
-        yv[s] = y;
-        v[0] = r * m1[s];
-        v[1] = r * y;
-        v[2] = r;
-        v[3] = r * r;
-        v[4] = q;
-    }
-    tile_partials<5>(S, T.row0 / TILE, v, lds);
-}
-
-// w, rho, beta, the projected residual and the stop test
-__global__ void k_fin_update(const int *seg_ids, Seg *segs, CgCtl ctl)
-{
-    const Seg &S = segs[seg_ids[blockIdx.x]];
-    if (S.sst->done) return;
-    __shared__ double lds[4 * 5];
-    double tot[5];
-    seg_total<5>(S, lds, tot);
-    if (threadIdx.x == 0) {
-        SegState *st = S.sst;
-        const double w = tot[0] / st->sdinv;
-        const double rho = tot[1] - w * tot[0];
-        const double res2 = (tot[3] - tot[2] * tot[2] / S.n) / S.n;
-        st->beta = rho / st->rho;
-        st->rho = rho;
-        st->w = w;
-        st->mshift -= w;
-        st->res = sqrt(fmax(res2, 0.0));
-        st->iters += 1;
-        st->iters_total += 1;
-        st->qshift = (S.Q - tot[4]) / S.n;
-        if (st->res < ctl.tol) st->done = 1;
-        else if (st->iters >= ctl.maxit) { st->done = 1; atomicOr(&st->status, ST_NOCONV); }
     }
 }
 
