@@ -317,14 +317,15 @@ int server_tick(ctbop_server *S, const Params<R> &prm, int cg_iters, bool poll)
         hipLaunchKernelGGL((k_build<R, BUILD_L>), g, b, 0, st, T, S->dsegs, prm);
         hipLaunchKernelGGL(k_rev, g, b, 0, st, T, S->dsegs);
         hipLaunchKernelGGL(k_mark_built, dim3((nis + 63) / 64), dim3(64), 0, st, sid, S->dsegs, nis);
-        // covalent energy and forces need only the lists: side stream
+        hipLaunchKernelGGL((k_assemble<R, LPR>), g, b, 0, st, T, S->dsegs, ctx->pd);
+        hipLaunchKernelGGL((k_hslice<R>), g, b, 0, st, T, S->dsegs);
+        // covalent energy and forces need only the lists: side stream, forked
+        // after the sliced copy so that they run beside the solve
         HIPCHK(hipEventRecord(S->ev_fork, st));
         HIPCHK(hipStreamWaitEvent(S->side, S->ev_fork, 0));
         hipLaunchKernelGGL((k_bond<R>), g, b, 0, S->side, T, S->dsegs, ctx->pd);
         hipLaunchKernelGGL((k_force_cov<R>), g, b, 0, S->side, T, S->dsegs, prm, 0);
         HIPCHK(hipEventRecord(S->ev_join, S->side));
-        hipLaunchKernelGGL((k_assemble<R, LPR>), g, b, 0, st, T, S->dsegs, ctx->pd);
-        hipLaunchKernelGGL((k_hslice<R>), g, b, 0, st, T, S->dsegs);
         CgCtl ctl{ctx->opts.cg_tol, ctx->opts.cg_maxit};
         hipLaunchKernelGGL(k_fin_w0, gs, b, 0, st, sid, S->dsegs);
         hipLaunchKernelGGL(k_shift_stats, g, b, 0, st, T, S->dsegs);
