@@ -579,8 +579,9 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
         // so that at most two of their blocks per CU take room from the
         // product (all at once they slowed its launches 1.6x; chunks of 1, 1.5,
         // 2, 3 and 4 blocks per CU: the step 12.96, 11.61, 10.97, 11.05 and
-        // 11.15 ms against 11.13); alone on the caller's stream, one launch
-        const int chunk = P.own ? ctx->side_chunk : nt;
+        // 11.15 ms against 11.13); with the charge coupling, whose assembly
+        // waits for them, and alone on the caller's stream, one launch
+        const int chunk = P.own && !fq ? ctx->side_chunk : nt;
         {
             Timed t(ctx, 3, cst);
             for (int t0 = 0; t0 < nt; t0 += chunk)
