@@ -229,35 +229,37 @@ __global__ void __launch_bounds__(TILE) k_assemble(const Tile *tiles, Seg *segs,
 // product, and the block-Jacobi preconditioner.  Each block first orders its
 // tile's rows by decreasing length (the slot order, hperm), then transposes
 // the tile one slice (SLICE slots) at a time through LDS, in chunks of HS_CH
-// entries per row: four lanes read one row's chunk as whole 128-byte lines
-// of hidx and Hr, and add the entries whose neighbour lies in the row's own
-// BK-row block into that block row in LDS, the four lanes in turn (so the
-// additions keep list order); then every lane writes entries of its slot as
-// slice columns (64 lanes store contiguous memory).  The tile's
-// blocks (J on the diagonal) are then inverted in LDS by Gauss-Jordan
-// elimination in FP32 (H is SPD and its blocks well conditioned, so no
-// pivoting; the preconditioner only has to be symmetric positive definite,
-// its accuracy sets the iteration count, not the solution), symmetrised and
-// written with their row sums; the tile's partial sums of r m1 and m1 start
-// the projection.
-constexpr int HS_CH = 32;                // entries per row and chunk (4 lanes x 8)
+// entries per row: four lanes read one row's chunk, 16 bytes each, of hidx
+// and Hr (chunks of 16 rather than 32 entries keep the block's LDS under
+// 40 KB, four blocks per CU: 736 -> 693 us), and add the entries whose
+// neighbour lies in the row's own BK-row block into that block row in LDS,
+// the four lanes in turn (so the additions keep list order); then every lane
+// writes entries of its slot as slice columns (64 lanes store contiguous
+// memory).  The tile's blocks (J on the diagonal) are then inverted in LDS by
+// Gauss-Jordan elimination in FP32 (H is SPD and its blocks well conditioned,
+// so no pivoting; the preconditioner only has to be symmetric positive
+// definite, its accuracy sets the iteration count, not the solution),
+// symmetrised and written with their row sums; the tile's partial sums of
+// r m1 and m1 start the projection.
+constexpr int HS_CH = 16;                // entries per row and chunk (4 lanes x 4)
+constexpr int HS_E = HS_CH / 4;
 constexpr int HS_LPR = 4;                // lanes reading one row's chunk
 
-// entries e0 .. e0+7 of a row-major row (fewer when the row ends first)
+// entries e0 .. e0+N-1 of a row-major row (fewer when the row ends first)
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-template <typename T>
-__device__ __forceinline__ void load8(const __attribute__((address_space(1))) T *row, int e0, int cnt, bool vec,
-                                      T (&out)[8])
+template <int N, typename T>
+__device__ __forceinline__ void loadN(const __attribute__((address_space(1))) T *row, int e0, int cnt, bool vec,
+                                      T (&out)[N])
 {
-    if (vec && e0 + 8 <= cnt) {
+    if (vec && e0 + N <= cnt) {
         const __attribute__((address_space(1))) u32x4 *src = (const __attribute__((address_space(1))) u32x4 *)(row + e0);
-        u32x4 w[8 * sizeof(T) / 16];
+        u32x4 w[N * sizeof(T) / 16];
 #pragma unroll
-        for (int k = 0; k < (int)(8 * sizeof(T) / 16); k++) w[k] = src[k];
+        for (int k = 0; k < (int)(N * sizeof(T) / 16); k++) w[k] = src[k];
         memcpy(out, w, sizeof out);
     } else {
 #pragma unroll
-        for (int k = 0; k < 8; k++) out[k] = e0 + k < cnt ? row[e0 + k] : (T)0;
+        for (int k = 0; k < N; k++) out[k] = e0 + k < cnt ? row[e0 + k] : (T)0;
     }
 }
 
@@ -341,16 +343,16 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
         const size_t b0 = slice_base(sbase + wl, S.Wl);
         float *arow = &A[rrk / BK][rrk % BK][0];
         for (int E0 = 0; E0 < mlen; E0 += HS_CH) {
-            const int e0 = E0 + rq * 8;
+            const int e0 = E0 + rq * HS_E;
             if (e0 < rcnt) {
-                uint32_t ie[8];
-                R ve[8];
-                load8(irow, e0, rcnt, vec, ie);
-                load8(vrow, e0, rcnt, vec, ve);
+                uint32_t ie[HS_E];
+                R ve[HS_E];
+                loadN<HS_E>(irow, e0, rcnt, vec, ie);
+                loadN<HS_E>(vrow, e0, rcnt, vec, ve);
 #pragma unroll
-                for (int k = 0; k < 8; k++) {
-                    ci[rl][rq * 8 + k] = ie[k];
-                    cv[rl][rq * 8 + k] = ve[k];
+                for (int k = 0; k < HS_E; k++) {
+                    ci[rl][rq * HS_E + k] = ie[k];
+                    cv[rl][rq * HS_E + k] = ve[k];
                 }
                 // entries whose neighbour lies in the row's own block, added
                 // into its block row by the row's four lanes in turn (the
@@ -359,7 +361,7 @@ __global__ void __launch_bounds__(TILE) k_hslice(const Tile *tiles, Seg *segs)
                 for (int q4 = 0; q4 < HS_LPR; q4++) {
                     if (rq == q4) {
 #pragma unroll
-                        for (int k = 0; k < 8; k++) {
+                        for (int k = 0; k < HS_E; k++) {
                             const unsigned col = (unsigned)((int)(ie[k] & J_MASK) - rbb);
                             if (e0 + k < rcnt && col < (unsigned)BK) arow[col] += (float)ve[k];
                         }
