@@ -622,10 +622,11 @@ int launch_eval(ctbop_ctx *ctx, Prep &P, const Params<R> &prm, int flags, int *i
         if (rc) return rc;
     }
     hipLaunchKernelGGL(k_fin_w0, g1, b, 0, st, sid, P.dseg);
-    hipLaunchKernelGGL(k_shift_stats, g, b, 0, st, P.dtiles, P.dseg);
-    hipLaunchKernelGGL(k_fin_assemble, g1, b, 0, st, sid, P.dseg, ctl);
-    if (!fq) {
-        // the single-reduction solve's start: the residual's last shift, y = M r
+    if (fq) {
+        hipLaunchKernelGGL(k_shift_stats, g, b, 0, st, P.dtiles, P.dseg);
+        hipLaunchKernelGGL(k_fin_assemble, g1, b, 0, st, sid, P.dseg, ctl);
+    } else {
+        // the single-reduction solve's start: the residual's shift, y = M r
         Timed t(ctx, 6, st);
         hipLaunchKernelGGL((k_cg1_update<true>), g, b, 0, st, P.dtiles, P.dseg);
     }

@@ -470,7 +470,12 @@ __device__ __forceinline__ double block_apply(const _Float16 *binv, int s, doubl
     return y;
 }
 
-// First pass over the starting residual: its M-weighted mean w0 = 1^T M r / 1^T M 1.
+// First pass over the starting residual: its M-weighted mean w0 = 1^T M r /
+// 1^T M 1, and the start of the single-reduction solve, whose first update
+// shifts r by w0 (the shift left by rounding is measured by its first
+// finalize and removed with the next update's shift; the charge coupling's
+// solve and the adjoint take a second pass instead, k_shift_stats and
+// k_fin_assemble, which set the state again).
 __global__ void k_fin_w0(const int *seg_ids, Seg *segs)
 {
     const Seg &S = segs[seg_ids[blockIdx.x]];
@@ -485,6 +490,11 @@ __global__ void k_fin_w0(const int *seg_ids, Seg *segs)
         st->nnz_wide = tot[2];
         st->nnz_slots = tot[3];
         st->nnz_halo = tot[5];
+        st->mshift = st->mu_prev - st->w;
+        st->iters = 0;
+        st->qshift = 0.0;
+        st->cg_first = 1;
+        st->cg_last = 0;
     }
 }
 
@@ -824,7 +834,9 @@ __global__ void __launch_bounds__(TILE) k_cg1_fin(const int *seg_ids, Seg *segs,
         st->res = sqrt(fmax(rr / n, 0.0));
         st->qshift = (S.Q - t[P_UPD + 4]) / n;
         const bool first = st->cg_first != 0;
-        if (!first) {
+        if (first) {
+            st->res0 = st->res;
+        } else {
             st->iters += 1;
             st->iters_total += 1;
         }

@@ -326,10 +326,7 @@ int server_tick(ctbop_server *S, const Params<R> &prm, int cg_iters, bool poll)
         hipLaunchKernelGGL((k_bond<R>), g, b, 0, S->side, T, S->dsegs, ctx->pd);
         hipLaunchKernelGGL((k_force_cov<R>), g, b, 0, S->side, T, S->dsegs, prm, 0);
         HIPCHK(hipEventRecord(S->ev_join, S->side));
-        CgCtl ctl{ctx->opts.cg_tol, ctx->opts.cg_maxit};
         hipLaunchKernelGGL(k_fin_w0, gs, b, 0, st, sid, S->dsegs);
-        hipLaunchKernelGGL(k_shift_stats, g, b, 0, st, T, S->dsegs);
-        hipLaunchKernelGGL(k_fin_assemble, gs, b, 0, st, sid, S->dsegs, ctl);
         hipLaunchKernelGGL((k_cg1_update<true>), g, b, 0, st, T, S->dsegs);
     }
     {
