@@ -922,12 +922,22 @@ __global__ void __launch_bounds__(TILE) k_force_coul(const Tile *tiles, Seg *seg
             const int j = (int)(ent & J_MASK);
             const V4 lj = ld4<R>(xs, j);
             const double qj = qv[j] + qsh;
+            // every entry lies inside rc: the rows were selected by the
+            // assembly's distance test (entry_r).  With FP32 pair terms the
+            // distance is taken with the hardware square root (~1 ulp, as
+            // close as the FP32 pair function itself) and needs no test; the
+            // FP64 build keeps the test, as a select rather than a branch so
+            // that the loop body stays one block and the charge load issues
+            // beside the position load
             R3<R> d;
-            const double r = entry_r<R>(li, lj, dtab[ent >> CODE_SHIFT], d);
-            // every entry lies inside rc (the rows were selected by this same
-            // distance); a select rather than a branch keeps the loop body in
-            // one block, so the charge load issues beside the position load
-            const bool in = r < PD.rc;
+            double r;
+            if constexpr (sizeof(R) == 4) {
+                d = pair_vec<R>(li, lj, dtab[ent >> CODE_SHIFT]);
+                r = (double)__builtin_amdgcn_sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+            } else {
+                r = entry_r<R>(li, lj, dtab[ent >> CODE_SHIFT], d);
+            }
+            const bool in = sizeof(R) == 4 ? true : r < PD.rc;
             double dCr, c;
             if constexpr (sizeof(R) == 4) {
                 float d32;
