@@ -641,11 +641,10 @@ __device__ __forceinline__ double spmv_row_halo(const double *hp, const uint16_t
     return a;
 }
 
-// What the product kernel computes besides s = H p: the plain solve's p^T s;
-// with the f_q coupling also p^T r (the line search); in the single-reduction
-// solve the product of y = M r instead, into hz, with the six sums its
-// finalize needs.
-enum SpmvMode { SP_PLAIN = 0, SP_FQ = 1, SP_CG1 = 2 };
+// What the product kernel computes: for the f_q coupling's nonlinear solve
+// s = H p with p^T s and p^T r (the line search); for the single-reduction
+// solve H y of y = M r, into hz, with the six sums its finalize needs.
+enum SpmvMode { SP_FQ = 1, SP_CG1 = 2 };
 constexpr int P_UPD = 0;    // single-reduction solve: partials 0..7 from the update,
 constexpr int P_PRD = 8;    // 8..13 from the product
 constexpr int P_CG1 = 14;   // partials the finalize adds up
@@ -656,7 +655,7 @@ constexpr int P_CG1 = 14;   // partials the finalize adds up
 // first stages p of its tile's halo in LDS; a slice of halo positions then
 // reads 6 bytes per entry from memory and p from LDS.  Slices of 16-bit
 // offsets (the halo did not fit) or full entries gather p from memory.
-template <typename R, int U, int MODE = SP_PLAIN>
+template <typename R, int U, int MODE>
 __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
 {
     const Tile T = my_tile(tiles);
@@ -721,17 +720,14 @@ __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
         } else {
             S.s[row] = y;
             v[0] = xs * y;
-            if (MODE == SP_FQ) v[1] = xs * rs;
+            v[1] = xs * rs;
         }
     }
     if (MODE == SP_CG1) {
         tile_partials_at<6>(S, tl, v, lds, P_PRD);
-    } else if (MODE == SP_FQ) {
+    } else {
         double w[2] = {v[0], v[1]};
         tile_partials<2>(S, tl, w, lds);
-    } else {
-        double w[1] = {v[0]};
-        tile_partials<1>(S, tl, w, lds);
     }
 }
 
@@ -746,7 +742,8 @@ __global__ void __launch_bounds__(TILE) k_spmv(const Tile *tiles, Seg *segs)
 // projected norm of the next residual, |r|^2 - 2 alpha r^T s + alpha^2 |s|^2
 // (each minus its mean part), from sums of the two kernels, so the solve
 // stops after the update that meets the tolerance without a further product.
-// An iteration is three launches: product (k_spmv, SP_CG1), finalize, update.
+// An iteration is four launches: product (k_spmv, SP_CG1), the finalize's two
+// stages (k_cg1_sum, k_cg1_fin), update.
 // ---------------------------------------------------------------------------
 
 // p <- y + beta p, s <- H y + beta s, q <- q + alpha p, r <- r - alpha s - c,
