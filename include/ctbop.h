@@ -109,7 +109,10 @@ typedef struct {
     int    long_cap;   /* Coulomb-list entries per atom (0: 512)                                  */
     int    short_cap;  /* covalent-list entries per atom (0: 64)                                  */
     int    fp64;       /* 1: every pair/triplet term in FP64 (default 0: FP32 terms, FP64 sums)   */
-    int    cg_check;   /* charge-solve iterations launched between convergence checks (0: 4)    */
+    int    cg_check;   /* charge-solve iterations launched between convergence checks (0: 4);
+                          the first batch of a solve on a system buffer is at least as long
+                          as that buffer's previous solve (iterations past convergence
+                          return at once on the device flag)                                */
     double fq_kappa;   /* charge-dependent covalent coupling (e^-2, >= 0; default 0 = off): the
                           paper's covalent-ionic mixed bond function f_q (Methods, first
                           paragraph) has its form in the authors' earlier paper; the stand-in

@@ -3,7 +3,8 @@
   - every request's E, F, q in a mixed batch of uneven sizes (8 to 3000
     atoms, clusters and periodic cells) is bitwise identical to the same
     request served alone, and to the single-system call;
-  - results match the CPU oracle within the mixed-precision tolerances;
+  - results match the CPU oracle within the mixed-precision tolerances,
+    also over the stream's whole size range (requests up to 20000 atoms);
   - with an arena that holds only a couple of requests at a time, admission
     waits for space (peak bytes stay within the arena) and results are
     unchanged;
@@ -89,6 +90,33 @@ def test_results_match_oracle(orc, theta, structs, alone):
     for s, a in list(zip(structs, alone))[:10]:
         if s.n > 1500:
             continue
+        Eo, Fo, qo, _ = orc.evaluate(s.pos, s.types, s.box, s.pbc, theta, tol=1e-13)
+        assert abs(a["E"] - Eo) / s.n < 1e-6
+        if np.linalg.norm(Fo) > 0:
+            assert np.linalg.norm(a["F"] - Fo) / np.linalg.norm(Fo) < 1e-5
+        assert np.abs(a["q"] - qo).max() < 1e-6
+
+
+def test_full_size_range_matches_oracle(ct, orc, theta):
+    """Requests over the serving stream's whole size range, up to its largest
+    (a 20000-atom cluster and a 20000-atom periodic cell), served in one mixed
+    batch: each matches the oracle and, bit for bit, the single-system call."""
+    from paper_1802_07871_amd.serving import Server
+    reqs = G.serving_requests(12, seed=19, nmax=20000)
+    reqs[0].update(n=20000, periodic=False)
+    reqs[1].update(n=20000, periodic=True)
+    structs = [G.request_structure(r) for r in reqs]
+    print(f"[serving] full size range: {[s.n for s in structs]}", flush=True)
+    srv = Server(ct.Potential(theta), 4 << 30, max_slots=64)
+    tickets = [srv.submit(s.pos, s.types, s.box, s.pbc) for s in structs]
+    got = srv.wait_all(tickets)
+    srv.close()
+    pot = ct.Potential(theta)
+    for s, t in zip(structs, tickets):
+        a = got[t]
+        assert a["status"] == 0
+        E, F, q, _ = pot.compute(s.pos, s.types, s.box, s.pbc, warm=False)
+        assert E == a["E"] and np.array_equal(F.cpu().numpy(), a["F"]) and np.array_equal(q.cpu().numpy(), a["q"])
         Eo, Fo, qo, _ = orc.evaluate(s.pos, s.types, s.box, s.pbc, theta, tol=1e-13)
         assert abs(a["E"] - Eo) / s.n < 1e-6
         if np.linalg.norm(Fo) > 0:
