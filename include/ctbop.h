@@ -105,7 +105,7 @@ typedef struct ctbop_ctx ctbop_ctx;
 typedef struct {
     double cg_tol;     /* stop when RMS of the projected charge residual < cg_tol (eV/e); default 1e-9 */
     int    cg_maxit;   /* default 500                                                            */
-    double skin;       /* Verlet skin (Angstrom): lists are rebuilt once an atom moved skin/2; 0.5 */
+    double skin;       /* Verlet skin (Angstrom): lists are rebuilt once an atom moved skin/2; 0.6 */
     int    long_cap;   /* Coulomb-list entries per atom (0: 512)                                  */
     int    short_cap;  /* covalent-list entries per atom (0: 64)                                  */
     int    fp64;       /* 1: every pair/triplet term in FP64 (default 0: FP32 terms, FP64 sums)   */

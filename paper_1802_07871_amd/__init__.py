@@ -155,7 +155,7 @@ class System:
 class Potential:
     """A parameter set and solver options (a ctbop_ctx)."""
 
-    def __init__(self, params=None, cg_tol: float = 1e-9, cg_maxit: int = 500, skin: float = 0.5,
+    def __init__(self, params=None, cg_tol: float = 1e-9, cg_maxit: int = 500, skin: float = 0.6,
                  long_cap: int = 512, short_cap: int = 64, fp64: bool = False, cg_check: int = 4,
                  fq_kappa: float = 0.0):
         if params is None:

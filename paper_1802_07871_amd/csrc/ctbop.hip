@@ -761,7 +761,7 @@ void ctbop_default_opts(ctbop_opts *o)
 {
     o->cg_tol = 1e-9;
     o->cg_maxit = 500;
-    o->skin = 0.5;
+    o->skin = 0.6;
     o->long_cap = 512;
     o->short_cap = 64;
     o->fp64 = 0;

@@ -80,7 +80,7 @@ def test_neighbour_lists_equal_brute_force(ct, orc, theta, name):
     sysb = pot.system(s.n, s.box, s.pbc)
     pot.compute(s.pos, s.types, s.box, s.pbc, sysbuf=sysb)
     (cl, jl, dl), (cs, js, ds) = pot.debug_lists(sysb)
-    rl = theta[P.index("rc_coul")] + 0.5
+    rl = theta[P.index("rc_coul")] + pot.opts.skin
     c, j, d = orc.neighbors(s.pos, s.box, s.pbc, rl, method=0)
     off = np.concatenate([[0], np.cumsum(c)])
     ref = {}
@@ -142,9 +142,9 @@ def test_warm_start_and_determinism(ct, orc, theta):
     assert i4["rebuilt"] == 0 and i4["cg_iters"] < i1["cg_iters"]
     Eo, Fo, qo, _ = orc.evaluate(pos, s.types, s.box, s.pbc, theta, tol=1e-13)
     assert np.linalg.norm(F4.cpu().numpy() - Fo) / np.linalg.norm(Fo) < 1e-5
-    # one atom moved past half the skin: rebuild
+    # one atom moved past half the skin (0.3 A by default): rebuild
     pos = pos.copy()
-    pos[0] += np.array([0.3, 0.0, 0.0])
+    pos[0] += np.array([0.45, 0.0, 0.0])
     _, F5, _, i5 = pot.compute(pos, s.types, s.box, s.pbc, warm=True)
     assert i5["rebuilt"] == 1
     Eo, Fo, qo, _ = orc.evaluate(pos, s.types, s.box, s.pbc, theta, tol=1e-13)
