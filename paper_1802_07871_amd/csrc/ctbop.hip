@@ -27,7 +27,7 @@ using namespace ctbop;
 namespace {
 
 constexpr int LPR = 16;             // lanes per Coulomb row (assembly, force gather)
-constexpr int BUILD_L = 8;          // lanes per atom in the list build (one cell's atoms at a time)
+constexpr int BUILD_L = 4;          // lanes per atom in the list build (tuned: 2, 4, 8, 16 lanes)
 constexpr int SPMV_U = 8;           // list entries in flight per row in the charge-solve product (tuned)
 
 thread_local std::string g_err;
