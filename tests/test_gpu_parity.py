@@ -268,6 +268,30 @@ def test_caller_stream_orders_results(ct, theta):
     assert bool((runs[0][0] == runs[1][0]).all()) and np.array_equal(runs[0][1], runs[1][1])
 
 
+@pytest.mark.parametrize("name", ["periodic 1000", "stepped slab"])
+def test_skin_does_not_change_results(ct, theta, name):
+    """The Verlet skin only sets how often the lists are rebuilt: each step
+    keeps the entries inside rc (and the bonds inside S) whatever the skin.
+    A different skin changes the cell grid, and with it the sorted order,
+    the order of the sums and the preconditioner's blocks, so the results
+    agree to rounding and the solve's tolerance (FP64 build, solved to
+    1e-13): 1e-10 in energy per atom, relative forces and charges."""
+    s = CASES[name]
+    out = []
+    for skin in (0.3, 0.6, 1.0):
+        print(f"[skin] {name} skin={skin}", flush=True)
+        E, F, q, info = ct.Potential(theta, fp64=True, cg_tol=1e-13, skin=skin).compute(
+            s.pos, s.types, s.box, s.pbc, warm=False)
+        assert info["status"] == 0
+        out.append((E, F.cpu().numpy(), q.cpu().numpy(), info["nnz_long"]))
+    E0, F0, q0, n0 = out[0]
+    for E, F, q, n in out[1:]:
+        assert n > n0                      # the wider skin holds more list entries
+        assert abs(E - E0) / s.n <= 1e-10
+        assert np.linalg.norm(F - F0) / np.linalg.norm(F0) <= 1e-10
+        assert np.abs(q - q0).max() <= 1e-10
+
+
 @pytest.mark.parametrize("fp64", [False, True])
 def test_row_width_does_not_change_results(ct, theta, fp64):
     """The Coulomb rows are stored with the list width as their stride; the
