@@ -15,8 +15,10 @@ recurrences):
     rounding: 5 % of the tolerance here);
   - the solve stops at the first update that meets the tolerance: a solve
     that took k iterations fails to converge within an iteration limit of
-    k - 1 from the same start.
-FP64 build, tolerance 1e-10.
+    k - 1 from the same start;
+  - the host's batching of iterations between its reads of the stop flag
+    changes neither the iterations nor the bits of the result.
+FP64 build, tolerance 1e-10, unless stated.
 """
 import copy
 
@@ -98,3 +100,23 @@ def test_warm_start_residual(ct, orc, theta):
     moved.pos = pos
     res = _true_residual(orc, theta, moved, q.cpu().numpy())
     assert res < TOL and abs(res - i2["cg_residual"]) < 0.05 * TOL
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_iteration_batching_does_not_change_results(ct, theta, prec):
+    """The host launches solver iterations in batches and reads the device's
+    flag between them; iterations launched after the solve converged return
+    at once.  Batches of 1, 4 and 64 iterations (a fresh context each, so
+    the first batch is not sized by an earlier solve) give the same
+    iterations and the same bits."""
+    s = CASES["stepped slab"]
+    out = []
+    for check in (1, 4, 64):
+        print(f"[solve] batches of {check} ({prec})", flush=True)
+        E, F, q, info = ct.Potential(theta, fp64=(prec == "fp64"), cg_check=check).compute(
+            s.pos, s.types, s.box, s.pbc, warm=False)
+        assert info["status"] == 0
+        out.append((E, F.cpu().numpy(), q.cpu().numpy(), info["cg_iters"]))
+    for E, F, q, it in out[1:]:
+        assert it == out[0][3]
+        assert E == out[0][0] and np.array_equal(F, out[0][1]) and np.array_equal(q, out[0][2])
