@@ -4,7 +4,8 @@
     atoms, clusters and periodic cells) is bitwise identical to the same
     request served alone, and to the single-system call;
   - results match the CPU oracle within the mixed-precision tolerances,
-    also over the stream's whole size range (requests up to 20000 atoms);
+    also over the stream's whole size range (requests up to 20000 atoms),
+    and to 1e-10 with an FP64 context;
   - with an arena that holds only a couple of requests at a time, admission
     waits for space (peak bytes stay within the arena) and results are
     unchanged;
@@ -122,6 +123,29 @@ def test_full_size_range_matches_oracle(ct, orc, theta):
         if np.linalg.norm(Fo) > 0:
             assert np.linalg.norm(a["F"] - Fo) / np.linalg.norm(Fo) < 1e-5
         assert np.abs(a["q"] - qo).max() < 1e-6
+
+
+def test_fp64_server_matches_oracle(ct, orc, theta):
+    """The server on an FP64 context (FP64 pair terms, charges solved to
+    1e-13): a mixed batch of clusters and periodic cells, each request
+    against the oracle to 1e-10 (energy per atom, relative forces,
+    charges)."""
+    from paper_1802_07871_amd.serving import Server
+    reqs = G.serving_requests(8, seed=23, nmax=2500)
+    structs = [G.request_structure(r) for r in reqs]
+    print(f"[serving] fp64 batch: {[s.n for s in structs]}", flush=True)
+    srv = Server(ct.Potential(theta, fp64=True, cg_tol=1e-13), 1 << 30, max_slots=16)
+    tickets = [srv.submit(s.pos, s.types, s.box, s.pbc) for s in structs]
+    got = srv.wait_all(tickets)
+    srv.close()
+    for s, t in zip(structs, tickets):
+        a = got[t]
+        assert a["status"] == 0
+        Eo, Fo, qo, _ = orc.evaluate(s.pos, s.types, s.box, s.pbc, theta, tol=1e-13)
+        assert abs(a["E"] - Eo) / s.n < 1e-10
+        if np.linalg.norm(Fo) > 0:
+            assert np.linalg.norm(a["F"] - Fo) / np.linalg.norm(Fo) < 1e-10
+        assert np.abs(a["q"] - qo).max() < 1e-10
 
 
 def test_admission_by_arena_budget(ct, theta, structs, alone):
