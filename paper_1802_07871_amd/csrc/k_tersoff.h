@@ -26,6 +26,16 @@ template <typename R> struct R3 { R x, y, z; };
 template <typename R>
 __device__ __forceinline__ R dev_sqrt(R v) { return sqrt(v); }
 
+// Reciprocal and square root of the covalent force terms: with FP32 terms the
+// hardware instructions (~1 ulp, as close as the FP32 terms themselves),
+// otherwise the correctly rounded operations.
+__device__ __forceinline__ float term_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+template <typename R>
+__device__ __forceinline__ R term_rcp(R x) { return (R)1 / x; }
+__device__ __forceinline__ float term_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <typename R>
+__device__ __forceinline__ R term_sqrt(R x) { return dev_sqrt(x); }
+
 __device__ __forceinline__ void dev_sincos(float a, float *s, float *c) { sincosf(a, s, c); }
 __device__ __forceinline__ void dev_sincos(double a, double *s, double *c) { sincos(a, s, c); }
 
@@ -46,7 +56,7 @@ template <typename R>
 __device__ __forceinline__ R angular(const Params<R> &P, int t, int l, R cs, R &dw)
 {
     const R x = P.h[t][l] - cs;
-    const R iden = (R)1 / (P.d2[t][l] + x * x);
+    const R iden = term_rcp(P.d2[t][l] + x * x);
     const R w = P.gam[t][l] * ((R)1 + P.c2d2[t][l] * x * x * iden);
     dw = -P.gam[t][l] * P.c2[t][l] * (R)2 * x * iden * iden;
     return w;
@@ -98,7 +108,7 @@ template <typename R>
 __device__ __forceinline__ void trip_grad(const Params<R> &P, int tc, int penv, const R3<R> &db, R rb,
                                           const R3<R> &de, R re, R3<R> gj[2], R3<R> gk[2])
 {
-    const R ib = (R)1 / rb, ie = (R)1 / re;
+    const R ib = term_rcp(rb), ie = term_rcp(re);
     const R3<R> ub = {db.x * ib, db.y * ib, db.z * ib};
     const R3<R> ue = {de.x * ie, de.y * ie, de.z * ie};
     const R cs = ub.x * ue.x + ub.y * ue.y + ub.z * ue.z;
@@ -390,7 +400,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
         const V4 lj = ld4<R>(xs, ent & J_MASK);
         pp = tm * 2 + (int)lj.w;
         d = pair_vec<R>(lm, lj, dtab[ent >> CODE_SHIFT]);
-        r = dev_sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
+        r = term_sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
     };
     auto bond = [&](int e, R3<R> &d, R &r, int &pp) {
         if (e < BOND_CACHE) {
@@ -420,7 +430,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
         R r;
         int pp;
         bond(e, d, r, pp);
-        const R ir = (R)1 / r;
+        const R ir = term_rcp(r);
         const V4 sv = ld4<R>(slot, slm + (size_t)e * SLICE);
         const R dv = pair_dvdr(P, pp, r, sv.x) * ir;
         R ax = dv * d.x, ay = dv * d.y, az = dv * d.z;
@@ -453,7 +463,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
         const int rv = cmap[slice_base(i, Ws) + (size_t)bsrev[slm + (size_t)e * SLICE] * SLICE];
         if (rv >= ni) continue;                               // (a reverse always exists)
         const R3<R> dmi = pair_vec<R>(lm, li, dtab[ent >> CODE_SHIFT]);
-        const R r = dev_sqrt(dmi.x * dmi.x + dmi.y * dmi.y + dmi.z * dmi.z), ir = (R)1 / r;
+        const R r = term_sqrt(dmi.x * dmi.x + dmi.y * dmi.y + dmi.z * dmi.z), ir = term_rcp(r);
         const R3<R> d = {-dmi.x, -dmi.y, -dmi.z};            // i -> m
         const size_t sli = slice_base(i, Wb);
         const V4 sv = ld4<R>(slot, sli + (size_t)rv * SLICE);
@@ -466,7 +476,7 @@ __global__ void __launch_bounds__(TILE) k_force_cov(const Tile *tiles, Seg *segs
             const V4 lk = ld4<R>(xs, ent2 & J_MASK);
             const int pk = ti * 2 + (int)lk.w;
             const R3<R> dk = pair_vec<R>(li, lk, dtab[ent2 >> CODE_SHIFT]);   // i -> k
-            const R rk = dev_sqrt(dk.x * dk.x + dk.y * dk.y + dk.z * dk.z);
+            const R rk = term_sqrt(dk.x * dk.x + dk.y * dk.y + dk.z * dk.z);
             R3<R> gj[2], gk[2];
             if (sv.y != (R)0 || sv.z != (R)0) {
                 // bond (i -> m), environment k: m is the partner j
